@@ -1,0 +1,127 @@
+/*
+ * xdrop.h - X-drop seed-and-extend alignment of long-read pairs on MI355X.
+ *
+ * The operation (paper: section 4 stage 4 and section 9 - every candidate
+ * read pair shares a retained k-mer, which seeds a pairwise alignment that is
+ * extended with the X-drop rule of section 2):
+ *
+ *   For task t with reads A = reads[pairs[2t]], B = reads[pairs[2t+1]] and the
+ *   shared k-mer starting at pa = seeds[2t] in A and pb = seeds[2t+1] in B:
+ *     seed  = sum_{u<k} (A[pa+u] == B[pb+u] ? match : mismatch)   (ungapped)
+ *     right = X-drop extension of A[pa+k..] against B[pb+k..]
+ *     left  = X-drop extension of reversed A[..pa) against reversed B[..pb)
+ *     score = left.best + seed + right.best
+ *     beg   = (pa - left.i, pb - left.j),  end = (pa+k+right.i, pb+k+right.j)
+ *   with half-open 0-based read coordinates.
+ *
+ *   One extension of a[1..m] against b[1..n], linear gaps: antidiagonal
+ *   d = i + j runs 1..m+n; a cell is evaluated when at least one of its
+ *   predecessors (i-1,j-1), (i-1,j), (i,j-1) is live, takes the maximum over
+ *   its live predecessors of S(i-1,j-1) + (a_i == b_j ? match : mismatch),
+ *   S(i-1,j) + gap, S(i,j-1) + gap, and is live when that score is at least
+ *   T_{d-1} - X, where T_{d-1} is the best live score on antidiagonals < d
+ *   (T_0 = S(0,0) = 0).  best = the final T; (i, j) = the live cell first
+ *   reaching it (earliest antidiagonal, then smallest i); the sweep ends once
+ *   two consecutive antidiagonals hold no live cell.  `cells` counts the
+ *   evaluated cells of both extensions (the seed is not counted); it is the
+ *   GCUPS numerator.
+ *
+ * Scores, coordinates and cell counts are exact integers: identical to the
+ * reference definition above bit for bit.
+ *
+ * Read store layout (device, owned by the library): base codes A=0 C=1 G=2
+ * T=3, 2 bits each, 16 bases per little-endian uint32 word (base u of read r
+ * is bits 2*(u%16) .. 2*(u%16)+1 of word word_off[r] + u/16).  Every read
+ * starts on a 16-word (64-byte) boundary and is zero-padded to one.
+ *
+ * Errors: functions return XD_OK (0) or a negative XD_E* code;
+ * xd_last_error() gives a message for the calling thread's last failure.
+ * Per-task problems do not fail a batch: they set that task's status.
+ */
+#ifndef XDROP_H
+#define XDROP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define XD_OK 0
+#define XD_EINVAL (-1)  /* bad argument; nothing was enqueued */
+#define XD_ENOMEM (-2)  /* device or host allocation failed */
+#define XD_EDEVICE (-3) /* a HIP call failed; see xd_last_error() */
+#define XD_EAGAIN (-4)  /* server: result not ready / request queue full */
+
+/* per-task status */
+#define XD_TASK_OK 0
+#define XD_TASK_BAD_READ 1 /* a read id >= n_reads */
+#define XD_TASK_BAD_SEED 2 /* pa + k > len(A) or pb + k > len(B) */
+#define XD_TASK_BAD_X 3    /* X < 0 or X > XD_X_MAX */
+#define XD_TASK_BAND_OVERFLOW 4 /* the live band outgrew the widest register window
+                                   (1024 cells); no result is produced */
+
+/* limits (checked; violations return XD_EINVAL) */
+#define XD_X_MAX (1 << 20)           /* largest X */
+#define XD_SCORE_LIMIT 127           /* 1 <= match <= 127, -127 <= mismatch < match, -127 <= gap <= -1 */
+#define XD_READ_MAX (1u << 22)       /* longest read, bases */
+
+typedef struct xd_store xd_store;
+
+/* ---- read store ---------------------------------------------------------- */
+
+/* Packs base codes (uint8 0..3, reads concatenated: read r is
+ * codes[off[r] .. off[r]+len[r])) into the store layout above, on the host.
+ * Pass words = NULL to get the required word count in *n_words (and the
+ * word offsets in word_off, which may also be NULL).  Codes > 3 -> XD_EINVAL. */
+int xd_pack_reads(const uint8_t* codes, const uint64_t* off, const uint32_t* len,
+                  uint32_t n_reads, uint32_t* words, uint64_t* word_off, uint64_t* n_words);
+
+/* Copies a packed read set (host pointers, store layout) to the current HIP
+ * device.  The store owns its device memory until xd_store_destroy().  It is
+ * read-only afterwards and may be used from several streams at once. */
+int xd_store_create(const uint32_t* words, uint64_t n_words, const uint64_t* word_off,
+                    const uint32_t* len, uint32_t n_reads, xd_store** out);
+
+/* Same, from unpacked base codes (packs on the host, then uploads). */
+int xd_store_create_from_codes(const uint8_t* codes, const uint64_t* off, const uint32_t* len,
+                               uint32_t n_reads, xd_store** out);
+
+void xd_store_destroy(xd_store* store);
+
+/* Device bytes held, read count, longest read. Any out pointer may be NULL. */
+int xd_store_info(const xd_store* store, uint64_t* device_bytes, uint32_t* n_reads,
+                  uint32_t* max_len);
+
+/* ---- batch alignment ----------------------------------------------------- */
+
+/* Aligns n tasks, one launch sequence per call (the plain form).
+ *
+ * Device pointers, caller-owned, valid until the stream reaches the work:
+ *   pairs  uint32[2n]  (ra, rb) per task
+ *   seeds  uint32[2n]  (pa, pb): 0-based k-mer start in ra and rb
+ *   x      int32[n]    X per task, or NULL to use x_scalar for every task
+ *   score  int32[n]    out; INT32_MIN when status != 0
+ *   beg    uint32[2n]  out; (beg_a, beg_b), 0 when status != 0
+ *   end    uint32[2n]  out; (end_a, end_b) half-open, 0 when status != 0
+ *   status int32[n]    out; XD_TASK_*
+ *   cells  uint64[n]   out, may be NULL; evaluated cells, 0 when status != 0
+ * hip_stream: a hipStream_t (NULL = the default stream).  The call is
+ * asynchronous: it validates the scalar arguments, enqueues kernels and a
+ * stream-ordered scratch allocation, and returns.  k >= 1.  n = 0 is a no-op.
+ * Invalid scalars (k, scores, x_scalar when x == NULL) -> XD_EINVAL, nothing
+ * enqueued. */
+int xd_align_batch(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,
+                   const int32_t* x, int32_t x_scalar, uint64_t n, int32_t k, int32_t match,
+                   int32_t mismatch, int32_t gap, int32_t* score, uint32_t* beg, uint32_t* end,
+                   int32_t* status, uint64_t* cells, void* hip_stream);
+
+/* Message for the calling thread's most recent failing call ("" if none). */
+const char* xd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XDROP_H */

@@ -1,0 +1,142 @@
+"""X-drop seed-and-extend alignment of long-read pairs on MI355X.
+
+Thin Python binding over libxdrop.so (C ABI in include/xdrop.h).  Every step
+of the alignment runs in the library's HIP kernels; this module only moves
+arguments: host arrays for the read store, torch device tensors for task
+inputs and results, and the caller's HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (READ_MAX, SCORE_LIMIT, TASK_BAD_READ, TASK_BAD_SEED, TASK_BAD_X,  # noqa
+                   TASK_BAND_OVERFLOW, TASK_OK, X_MAX, XdropError)
+
+
+def _p(a) -> ctypes.c_void_p:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(ctypes.c_void_p)
+    return ctypes.c_void_p(a.data_ptr())
+
+
+def pack_reads(codes, off, length):
+    """Host 2-bit packing (library routine) -> (words uint32, word_off uint64)."""
+    lib = _lib.load()
+    codes = np.ascontiguousarray(codes, np.uint8)
+    off = np.ascontiguousarray(off, np.uint64)
+    length = np.ascontiguousarray(length, np.uint32)
+    n = ctypes.c_uint64(0)
+    _lib.check(lib.xd_pack_reads(_p(codes), _p(off), _p(length), length.size, None, None,
+                                 ctypes.byref(n)))
+    words = np.zeros(max(int(n.value), 1), np.uint32)
+    woff = np.zeros(max(length.size, 1), np.uint64)
+    _lib.check(lib.xd_pack_reads(_p(codes), _p(off), _p(length), length.size, _p(words),
+                                 _p(woff), ctypes.byref(n)))
+    return words[:int(n.value)], woff[:length.size]
+
+
+class ReadStore:
+    """Device-resident 2-bit read store (xd_store)."""
+
+    def __init__(self, codes, off, length):
+        lib = _lib.load()
+        codes = np.ascontiguousarray(codes, np.uint8)
+        off = np.ascontiguousarray(off, np.uint64)
+        length = np.ascontiguousarray(length, np.uint32)
+        h = ctypes.c_void_p()
+        _lib.check(lib.xd_store_create_from_codes(_p(codes), _p(off), _p(length),
+                                                  length.size, ctypes.byref(h)))
+        self._h = h
+        self.n_reads = int(length.size)
+
+    @classmethod
+    def from_workload(cls, w):
+        return cls(w.codes, w.off, w.length)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("store is closed")
+        return self._h
+
+    def info(self):
+        b, n, mx = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32()
+        _lib.check(_lib.load().xd_store_info(self.handle, ctypes.byref(b), ctypes.byref(n),
+                                             ctypes.byref(mx)))
+        return dict(device_bytes=b.value, n_reads=n.value, max_len=mx.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.load().xd_store_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_dev(name, t, n_items, dtype_bytes):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if not t.is_contiguous() or t.element_size() != dtype_bytes or t.numel() != n_items:
+        raise ValueError("%s: need a contiguous %d-byte tensor with %d elements" %
+                         (name, dtype_bytes, n_items))
+
+
+def align_batch(store: ReadStore, pairs, seeds, x=None, x_scalar=0, k=17, match=1,
+                mismatch=-1, gap=-1, out=None, stream=None, with_cells=True):
+    """Aligns n tasks on the GPU (xd_align_batch).
+
+    pairs, seeds: int32/uint32 device tensors [n, 2]; x: int32 [n] or None.
+    Returns dict(score int32 [n], beg int32 [n,2], end int32 [n,2],
+    status int32 [n], cells int64 [n]) of device tensors (coordinates hold the
+    uint32 bit patterns).  Asynchronous on `stream` (default: current).
+    """
+    import torch
+    n = int(pairs.shape[0])
+    dev = pairs.device
+    _check_dev("pairs", pairs, 2 * n, 4)
+    _check_dev("seeds", seeds, 2 * n, 4)
+    if x is not None:
+        _check_dev("x", x, n, 4)
+    if out is None:
+        out = dict(score=torch.empty(n, dtype=torch.int32, device=dev),
+                   beg=torch.empty((n, 2), dtype=torch.int32, device=dev),
+                   end=torch.empty((n, 2), dtype=torch.int32, device=dev),
+                   status=torch.empty(n, dtype=torch.int32, device=dev),
+                   cells=torch.empty(n, dtype=torch.int64, device=dev) if with_cells else None)
+    lib = _lib.load()
+    _lib.check(lib.xd_align_batch(
+        store.handle, _p(pairs), _p(seeds), _p(x), int(x_scalar), n, int(k), int(match),
+        int(mismatch), int(gap), _p(out["score"]), _p(out["beg"]), _p(out["end"]),
+        _p(out["status"]), _p(out.get("cells")), _stream_ptr(stream)))
+    return out
+
+
+def workload_tensors(w, device="cuda"):
+    """Task arrays of a synth.Workload as device tensors (pairs, seeds, x)."""
+    import torch
+    pairs = torch.from_numpy(np.stack([w.ra, w.rb], 1).astype(np.int32)).to(device)
+    seeds = torch.from_numpy(np.stack([w.pa, w.pb], 1).astype(np.int32)).to(device)
+    x = torch.from_numpy(w.x.astype(np.int32)).to(device)
+    return pairs, seeds, x

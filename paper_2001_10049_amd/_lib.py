@@ -1,0 +1,65 @@
+"""ctypes declarations for libxdrop.so (include/xdrop.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxdrop.so")
+
+XD_OK, XD_EINVAL, XD_ENOMEM, XD_EDEVICE, XD_EAGAIN = 0, -1, -2, -3, -4
+TASK_OK, TASK_BAD_READ, TASK_BAD_SEED, TASK_BAD_X, TASK_BAND_OVERFLOW = 0, 1, 2, 3, 4
+X_MAX = 1 << 20
+SCORE_LIMIT = 127
+READ_MAX = 1 << 22
+
+# every symbol include/xdrop.h declares
+EXPORTS = (
+    "xd_pack_reads", "xd_store_create", "xd_store_create_from_codes", "xd_store_destroy",
+    "xd_store_info", "xd_align_batch", "xd_last_error",
+)
+
+
+class XdropError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("libxdrop error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libxdrop.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_2001_10049_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+    lib.xd_pack_reads.argtypes = [vp, vp, vp, u32, vp, vp, ctypes.POINTER(u64)]
+    lib.xd_pack_reads.restype = ctypes.c_int
+    lib.xd_store_create.argtypes = [vp, u64, vp, vp, u32, ctypes.POINTER(vp)]
+    lib.xd_store_create.restype = ctypes.c_int
+    lib.xd_store_create_from_codes.argtypes = [vp, vp, vp, u32, ctypes.POINTER(vp)]
+    lib.xd_store_create_from_codes.restype = ctypes.c_int
+    lib.xd_store_destroy.argtypes = [vp]
+    lib.xd_store_destroy.restype = None
+    lib.xd_store_info.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u32),
+                                  ctypes.POINTER(u32)]
+    lib.xd_store_info.restype = ctypes.c_int
+    lib.xd_align_batch.argtypes = [vp, vp, vp, vp, i32, u64, i32, i32, i32, i32, vp, vp, vp,
+                                   vp, vp, vp]
+    lib.xd_align_batch.restype = ctypes.c_int
+    lib.xd_last_error.argtypes = []
+    lib.xd_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(rc: int) -> int:
+    if rc < 0:
+        raise XdropError(rc, load().xd_last_error().decode(errors="replace"))
+    return rc

@@ -1,0 +1,423 @@
+// libxdrop: C ABI for X-drop seed-and-extend on MI355X (declared in
+// include/xdrop.h), with the batch kernels it launches.
+//
+// Batch pipeline (all stream-ordered on the caller's stream):
+//   1. k_reset      zero the overflow-list counters
+//   2. k_ext_first  one wavefront per extension (2 per task: left, right),
+//                   64-cell window; overflowing extensions go to list 1
+//   3. k_ext_list   persistent waves over list 1 with a 256-cell window,
+//                   overflow to list 2; then list 2 with a 1024-cell window
+//   4. k_combine    one thread per task: status, seed score, score,
+//                   coordinates, cells
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdarg.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "xdrop.h"
+#include "xdrop_device.h"
+
+using xd::ExtOut;
+
+namespace {
+
+constexpr uint32_t kMaxTier2Blocks = 2048;
+
+struct StoreDev {
+  const uint32_t* words;
+  const uint64_t* word_off;
+  const uint32_t* len;
+  uint32_t n_reads;
+};
+
+struct BatchArgs {
+  StoreDev st;
+  const uint32_t* pairs;
+  const uint32_t* seeds;
+  const int32_t* x;
+  int32_t x_scalar;
+  uint32_t n;
+  int32_t k;
+  xd::Scoring sc;
+  ExtOut* ext;       // [2n]
+  int32_t* score;
+  uint32_t* beg;
+  uint32_t* end;
+  int32_t* status;
+  uint64_t* cells;
+};
+
+// ---- per-task validation (shared by the extension and combine kernels) ----
+__device__ __forceinline__ int32_t task_status(const BatchArgs& A, uint32_t t, uint32_t& ra,
+                                               uint32_t& rb, uint32_t& pa, uint32_t& pb,
+                                               int32_t& X) {
+  ra = A.pairs[2 * (uint64_t)t];
+  rb = A.pairs[2 * (uint64_t)t + 1];
+  pa = A.seeds[2 * (uint64_t)t];
+  pb = A.seeds[2 * (uint64_t)t + 1];
+  X = A.x ? A.x[t] : A.x_scalar;
+  if (ra >= A.st.n_reads || rb >= A.st.n_reads) return XD_TASK_BAD_READ;
+  const uint64_t la = A.st.len[ra], lb = A.st.len[rb];
+  if ((uint64_t)pa + (uint64_t)A.k > la || (uint64_t)pb + (uint64_t)A.k > lb)
+    return XD_TASK_BAD_SEED;
+  if (X < 0 || X > XD_X_MAX) return XD_TASK_BAD_X;
+  return XD_TASK_OK;
+}
+
+// Sets up and runs extension e (task e/2; e even = left, odd = right) on the
+// calling wave.  Returns false if it overflowed this tier's window.
+template <int CPL, bool UNIT>
+__device__ bool run_ext(const BatchArgs& A, uint32_t e, uint32_t* ring) {
+  const uint32_t t = e >> 1;
+  uint32_t ra, rb, pa, pb;
+  int32_t X;
+  const int32_t st = task_status(A, t, ra, rb, pa, pb, X);
+  ra = __builtin_amdgcn_readfirstlane(ra);
+  rb = __builtin_amdgcn_readfirstlane(rb);
+  pa = __builtin_amdgcn_readfirstlane(pa);
+  pb = __builtin_amdgcn_readfirstlane(pb);
+  X = __builtin_amdgcn_readfirstlane(X);
+  if (__builtin_amdgcn_readfirstlane(st) != XD_TASK_OK) {
+    if (xd::lane_id() == 0) {
+      ExtOut o = {0, 0, 0, xd::kExtInvalid, 0};
+      A.ext[e] = o;
+    }
+    return true;
+  }
+  const int32_t la = (int32_t)__builtin_amdgcn_readfirstlane(A.st.len[ra]);
+  const int32_t lb = (int32_t)__builtin_amdgcn_readfirstlane(A.st.len[rb]);
+  xd::Ext ex;
+  ex.wa = A.st.words + A.st.word_off[ra];
+  ex.wb = A.st.words + A.st.word_off[rb];
+  ex.X = X;
+  if (e & 1) {  // right: suffixes after the seed, forwards
+    ex.oa = (int32_t)pa + A.k;
+    ex.ob = (int32_t)pb + A.k;
+    ex.dir = 1;
+    ex.m = la - ex.oa;
+    ex.n = lb - ex.ob;
+  } else {      // left: prefixes before the seed, backwards
+    ex.oa = (int32_t)pa - 1;
+    ex.ob = (int32_t)pb - 1;
+    ex.dir = -1;
+    ex.m = (int32_t)pa;
+    ex.n = (int32_t)pb;
+  }
+  ExtOut o;
+  if (!xd::extend<CPL, UNIT>(ex, A.sc, ring, o)) return false;
+  if (xd::lane_id() == 0) A.ext[e] = o;
+  return true;
+}
+
+__device__ __forceinline__ void push_list(uint32_t* list, uint32_t* count, uint32_t e) {
+  if (xd::lane_id() == 0) {
+    const uint32_t slot = atomicAdd(count, 1u);
+    list[slot] = e;
+  }
+}
+
+// counters: [0] list-1 size, [1] list-1 head, [2] list-2 size, [3] list-2
+// head, [4] list-3 size
+__global__ void k_reset(uint32_t* counters) {
+  if (threadIdx.x < 8) counters[threadIdx.x] = 0;
+}
+
+template <int CPL, bool UNIT>
+__global__ __launch_bounds__(64) void k_ext_first(BatchArgs A, uint32_t* ovf_list,
+                                                  uint32_t* ovf_count) {
+  __shared__ uint32_t ring[xd::Tier<CPL>::LDS_WORDS];
+  const uint32_t e = blockIdx.x;
+  if (!run_ext<CPL, UNIT>(A, e, ring)) push_list(ovf_list, ovf_count, e);
+}
+
+// Persistent waves working through a list of extensions (WAVES waves per
+// block, each with its own ring).
+template <int CPL, bool UNIT, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_ext_list(BatchArgs A, const uint32_t* list,
+                                                         const uint32_t* count, uint32_t* head,
+                                                         uint32_t* ovf_list,
+                                                         uint32_t* ovf_count) {
+  static_assert(WAVES * xd::Tier<CPL>::LDS_WORDS * 4 <= 64 * 1024, "LDS per block");
+  __shared__ uint32_t rings[WAVES][xd::Tier<CPL>::LDS_WORDS];
+  const int w = threadIdx.x >> 6;
+  const uint32_t total = __builtin_amdgcn_readfirstlane(*count);
+  for (;;) {
+    uint32_t idx = 0;
+    if (xd::lane_id() == 0) idx = atomicAdd(head, 1u);
+    idx = __shfl(idx, 0, 64);
+    idx = __builtin_amdgcn_readfirstlane(idx);
+    if (idx >= total) break;
+    const uint32_t e = list[idx];
+    if (!run_ext<CPL, UNIT>(A, e, rings[w])) {
+      if (ovf_list) {
+        push_list(ovf_list, ovf_count, e);
+      } else if (xd::lane_id() == 0) {
+        ExtOut o = {0, 0, 0, xd::kExtOverflow, 0};
+        A.ext[e] = o;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_combine(BatchArgs A) {
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= A.n) return;
+  uint32_t ra, rb, pa, pb;
+  int32_t X;
+  int32_t st = task_status(A, t, ra, rb, pa, pb, X);
+  const ExtOut L = A.ext[2 * (uint64_t)t];
+  const ExtOut R = A.ext[2 * (uint64_t)t + 1];
+  if (st == XD_TASK_OK && ((L.flags | R.flags) & xd::kExtOverflow)) st = XD_TASK_BAND_OVERFLOW;
+  if (st != XD_TASK_OK) {
+    A.score[t] = INT32_MIN;
+    A.beg[2 * (uint64_t)t] = 0;
+    A.beg[2 * (uint64_t)t + 1] = 0;
+    A.end[2 * (uint64_t)t] = 0;
+    A.end[2 * (uint64_t)t + 1] = 0;
+    A.status[t] = st;
+    if (A.cells) A.cells[t] = 0;
+    return;
+  }
+  const uint32_t* wa = A.st.words + A.st.word_off[ra];
+  const uint32_t* wb = A.st.words + A.st.word_off[rb];
+  int32_t seed = 0;
+  for (int32_t u = 0; u < A.k; ++u)
+    seed += (xd::code_at(wa, (int32_t)pa + u) == xd::code_at(wb, (int32_t)pb + u)) ? A.sc.M
+                                                                                    : A.sc.MM;
+  A.score[t] = L.best + seed + R.best;
+  A.beg[2 * (uint64_t)t] = pa - (uint32_t)L.bi;
+  A.beg[2 * (uint64_t)t + 1] = pb - (uint32_t)L.bj;
+  A.end[2 * (uint64_t)t] = pa + (uint32_t)A.k + (uint32_t)R.bi;
+  A.end[2 * (uint64_t)t + 1] = pb + (uint32_t)A.k + (uint32_t)R.bj;
+  A.status[t] = XD_TASK_OK;
+  if (A.cells) A.cells[t] = L.cells + R.cells;
+}
+
+template <bool UNIT>
+void launch_extensions(const BatchArgs& A, uint64_t n_ext, uint32_t* list1, uint32_t* list2,
+                       uint32_t* ctr, hipStream_t stream) {
+  hipLaunchKernelGGL((k_ext_first<1, UNIT>), dim3((uint32_t)n_ext), dim3(64), 0, stream, A,
+                     list1, ctr + 0);
+  hipLaunchKernelGGL((k_ext_list<4, UNIT, 4>), dim3(kMaxTier2Blocks), dim3(256), 0, stream, A,
+                     list1, ctr + 0, ctr + 1, list2, ctr + 2);
+  hipLaunchKernelGGL((k_ext_list<16, UNIT, 1>), dim3(kMaxTier2Blocks), dim3(64), 0, stream, A,
+                     list2, ctr + 2, ctr + 3, (uint32_t*)nullptr, (uint32_t*)nullptr);
+}
+
+// ---- errors -----------------------------------------------------------------
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? XD_ENOMEM : XD_EDEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                  \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+  } while (0)
+
+int check_scoring(int32_t k, int32_t match, int32_t mismatch, int32_t gap) {
+  if (k < 1) return fail(XD_EINVAL, "k must be >= 1 (got %d)", k);
+  if (match < 1 || match > XD_SCORE_LIMIT)
+    return fail(XD_EINVAL, "match must be in [1, %d] (got %d)", XD_SCORE_LIMIT, match);
+  if (mismatch >= match || mismatch < -XD_SCORE_LIMIT)
+    return fail(XD_EINVAL, "mismatch must be in [-%d, match) (got %d)", XD_SCORE_LIMIT,
+                mismatch);
+  if (gap > -1 || gap < -XD_SCORE_LIMIT)
+    return fail(XD_EINVAL, "gap must be in [-%d, -1] (got %d)", XD_SCORE_LIMIT, gap);
+  return XD_OK;
+}
+
+}  // namespace
+
+struct xd_store {
+  uint32_t* words = nullptr;
+  uint64_t* word_off = nullptr;
+  uint32_t* len = nullptr;
+  uint64_t n_words = 0;
+  uint32_t n_reads = 0;
+  uint32_t max_len = 0;
+  int device = 0;
+};
+
+extern "C" {
+
+const char* xd_last_error(void) { return g_err.c_str(); }
+
+int xd_pack_reads(const uint8_t* codes, const uint64_t* off, const uint32_t* len,
+                  uint32_t n_reads, uint32_t* words, uint64_t* word_off, uint64_t* n_words) {
+  if (!n_words || (n_reads && (!off || !len)))
+    return fail(XD_EINVAL, "xd_pack_reads: null pointer");
+  if (words && !codes && n_reads) return fail(XD_EINVAL, "xd_pack_reads: codes is null");
+  uint64_t pos = 0;
+  for (uint32_t r = 0; r < n_reads; ++r) {
+    if (len[r] > XD_READ_MAX)
+      return fail(XD_EINVAL, "read %u has %u bases (limit %u)", r, len[r], XD_READ_MAX);
+    if (word_off) word_off[r] = pos;
+    const uint64_t w = ((uint64_t)len[r] + 15) / 16;
+    pos += (w + 15) / 16 * 16;
+  }
+  if (words) {
+    if (!word_off) return fail(XD_EINVAL, "xd_pack_reads: word_off is null");
+    if (pos > *n_words) return fail(XD_EINVAL, "xd_pack_reads: words holds %llu, need %llu",
+                                    (unsigned long long)*n_words, (unsigned long long)pos);
+    memset(words, 0, pos * sizeof(uint32_t));
+    for (uint32_t r = 0; r < n_reads; ++r) {
+      const uint8_t* c = codes + off[r];
+      uint32_t* w = words + word_off[r];
+      for (uint32_t u = 0; u < len[r]; ++u) {
+        if (c[u] > 3) return fail(XD_EINVAL, "read %u base %u: code %u > 3", r, u, c[u]);
+        w[u >> 4] |= (uint32_t)c[u] << ((u & 15) * 2);
+      }
+    }
+  }
+  *n_words = pos;
+  return XD_OK;
+}
+
+int xd_store_create(const uint32_t* words, uint64_t n_words, const uint64_t* word_off,
+                    const uint32_t* len, uint32_t n_reads, xd_store** out) {
+  if (!out) return fail(XD_EINVAL, "xd_store_create: out is null");
+  *out = nullptr;
+  if (n_reads && (!word_off || !len)) return fail(XD_EINVAL, "xd_store_create: null arrays");
+  if (n_words && !words) return fail(XD_EINVAL, "xd_store_create: words is null");
+  uint32_t max_len = 0;
+  for (uint32_t r = 0; r < n_reads; ++r) {
+    if (len[r] > XD_READ_MAX)
+      return fail(XD_EINVAL, "read %u has %u bases (limit %u)", r, len[r], XD_READ_MAX);
+    const uint64_t need = word_off[r] + ((uint64_t)len[r] + 15) / 16;
+    if (need > n_words)
+      return fail(XD_EINVAL, "read %u ends at word %llu past n_words %llu", r,
+                  (unsigned long long)need, (unsigned long long)n_words);
+    if (len[r] > max_len) max_len = len[r];
+  }
+  xd_store* s = new xd_store();
+  s->n_words = n_words;
+  s->n_reads = n_reads;
+  s->max_len = max_len;
+  hipError_t e = hipGetDevice(&s->device);
+  const uint64_t wb = (n_words ? n_words : 1) * sizeof(uint32_t);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->words, wb);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->word_off, (n_reads ? n_reads : 1) * 8ull);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->len, (n_reads ? n_reads : 1) * 4ull);
+  if (e == hipSuccess && n_words)
+    e = hipMemcpy(s->words, words, n_words * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && n_reads)
+    e = hipMemcpy(s->word_off, word_off, n_reads * 8ull, hipMemcpyHostToDevice);
+  if (e == hipSuccess && n_reads) e = hipMemcpy(s->len, len, n_reads * 4ull, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    int rc = hip_fail(e, "xd_store_create");
+    xd_store_destroy(s);
+    return rc;
+  }
+  *out = s;
+  return XD_OK;
+}
+
+int xd_store_create_from_codes(const uint8_t* codes, const uint64_t* off, const uint32_t* len,
+                               uint32_t n_reads, xd_store** out) {
+  uint64_t n_words = 0;
+  int rc = xd_pack_reads(codes, off, len, n_reads, nullptr, nullptr, &n_words);
+  if (rc) return rc;
+  std::vector<uint32_t> words(n_words ? n_words : 1);
+  std::vector<uint64_t> woff(n_reads ? n_reads : 1);
+  rc = xd_pack_reads(codes, off, len, n_reads, words.data(), woff.data(), &n_words);
+  if (rc) return rc;
+  return xd_store_create(words.data(), n_words, woff.data(), len, n_reads, out);
+}
+
+void xd_store_destroy(xd_store* s) {
+  if (!s) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(s->device);
+  (void)hipFree(s->words);
+  (void)hipFree(s->word_off);
+  (void)hipFree(s->len);
+  (void)hipSetDevice(cur);
+  delete s;
+}
+
+int xd_store_info(const xd_store* s, uint64_t* device_bytes, uint32_t* n_reads,
+                  uint32_t* max_len) {
+  if (!s) return fail(XD_EINVAL, "xd_store_info: store is null");
+  if (device_bytes) *device_bytes = s->n_words * 4 + (uint64_t)s->n_reads * 12;
+  if (n_reads) *n_reads = s->n_reads;
+  if (max_len) *max_len = s->max_len;
+  return XD_OK;
+}
+
+int xd_align_batch(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,
+                   const int32_t* x, int32_t x_scalar, uint64_t n, int32_t k, int32_t match,
+                   int32_t mismatch, int32_t gap, int32_t* score, uint32_t* beg, uint32_t* end,
+                   int32_t* status, uint64_t* cells, void* hip_stream) {
+  if (!store) return fail(XD_EINVAL, "xd_align_batch: store is null");
+  int rc = check_scoring(k, match, mismatch, gap);
+  if (rc) return rc;
+  if (!x && (x_scalar < 0 || x_scalar > XD_X_MAX))
+    return fail(XD_EINVAL, "x_scalar must be in [0, %d] (got %d)", XD_X_MAX, x_scalar);
+  if (n == 0) return XD_OK;
+  if (n > (1ull << 30)) return fail(XD_EINVAL, "n = %llu exceeds 2^30", (unsigned long long)n);
+  if (!pairs || !seeds || !score || !beg || !end || !status)
+    return fail(XD_EINVAL, "xd_align_batch: null array");
+  hipStream_t stream = (hipStream_t)hip_stream;
+
+  BatchArgs A;
+  A.st = {store->words, store->word_off, store->len, store->n_reads};
+  A.pairs = pairs;
+  A.seeds = seeds;
+  A.x = x;
+  A.x_scalar = x_scalar;
+  A.n = (uint32_t)n;
+  A.k = k;
+  A.sc = {match, mismatch, gap};
+  A.score = score;
+  A.beg = beg;
+  A.end = end;
+  A.status = status;
+  A.cells = cells;
+
+  // scratch: extension results, two overflow lists, counters
+  const uint64_t n_ext = 2 * n;
+  const uint64_t ext_bytes = (n_ext * sizeof(ExtOut) + 255) & ~255ull;
+  const uint64_t list_bytes = (n_ext * 4 + 255) & ~255ull;
+  const uint64_t total = ext_bytes + 2 * list_bytes + 256;
+  char* scratch = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&scratch, total, stream));
+  A.ext = (ExtOut*)scratch;
+  uint32_t* list1 = (uint32_t*)(scratch + ext_bytes);
+  uint32_t* list2 = (uint32_t*)(scratch + ext_bytes + list_bytes);
+  uint32_t* ctr = (uint32_t*)(scratch + ext_bytes + 2 * list_bytes);
+
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, ctr);
+  if (match == 1) {
+    launch_extensions<true>(A, n_ext, list1, list2, ctr, stream);
+  } else {
+    launch_extensions<false>(A, n_ext, list1, list2, ctr, stream);
+  }
+  hipLaunchKernelGGL(k_combine, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, stream, A);
+  hipError_t le = hipGetLastError();
+  hipError_t fe = hipFreeAsync(scratch, stream);
+  if (le != hipSuccess) return hip_fail(le, "kernel launch");
+  if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
+  return XD_OK;
+}
+
+}  // extern "C"

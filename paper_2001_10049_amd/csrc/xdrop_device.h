@@ -1,0 +1,305 @@
+// X-drop extension on one wavefront (gfx950, wave64).
+//
+// One extension of a[1..m] against b[1..n] (paper section 2: linear-gap
+// alignment extended until the score drops X below the best seen; section 9:
+// one such alignment per seed of a candidate pair).  The rule implemented is
+// the one stated in include/xdrop.h.
+//
+// Mapping.  A wavefront owns a window of Q = 64*CPL consecutive rows of the
+// current antidiagonal: lane l, slot c holds row i = base + l*CPL + c.  Moving
+// from antidiagonal d-1 to d keeps the row of the "left" predecessor (i, j-1)
+// in the same lane/slot; the "up" predecessor (i-1, j) and the diagonal one
+// (i-1, j-1) sit one cell lower, which is one slot lower in the same lane or,
+// for slot 0, the last slot of the next lower lane (one DPP wave_shr:1).
+//
+// Scores are kept as U = S + g*d + bias (g = -gap > 0, d = antidiagonal):
+//   U(i,j) = max( U(i-1,j-1) + sub(a_i,b_j) - 2*gap,  U(i-1,j),  U(i,j-1) )
+// so the two gap moves cost nothing and the diagonal adds mismatch-2*gap plus
+// (match-mismatch) on a match.  Dead cells hold 0; every value derived from a
+// live cell stays above kEvMin and every value derived only from dead cells
+// stays below it, so "evaluated" is s > kEvMin and "live" is s >= thr with
+// thr = T_{d-1} - X + g*d + bias (a wave-uniform scalar).
+//
+// The window slides up (re-centres) when the live band nears its top, by a
+// whole number of lanes (ds_bpermute).  A band that cannot fit the window
+// within the next 4 antidiagonals makes the extension report overflow; the
+// caller re-runs it in a wider tier, so no result is ever truncated.
+//
+// b is read through a per-wave LDS ring of encoded bases:
+//   ring[j mod RING] = (match - mismatch) << (8 * code(b_j))
+// and a lane's own a_i is kept as 8*code(a_i), so one v_bfe_u32 gives the
+// match bonus of a cell.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace xd {
+
+constexpr int32_t kEvMin = 4096;  // evaluated cells have s > kEvMin
+constexpr int32_t kBias0 = 8192;  // bias = X + kBias0 keeps live U >= 8192
+
+struct ExtOut {
+  int32_t best;
+  int32_t bi, bj;
+  uint32_t flags;
+  uint64_t cells;
+};
+constexpr uint32_t kExtDone = 1u;
+constexpr uint32_t kExtOverflow = 2u;
+constexpr uint32_t kExtInvalid = 4u;
+
+struct Scoring {
+  int32_t M, MM, G;
+};
+
+// One extension's inputs.
+struct Ext {
+  const uint32_t* wa;  // first word of read A
+  const uint32_t* wb;  // first word of read B
+  int32_t oa, ob;      // position of a_1 in A, of b_1 in B
+  int32_t dir;         // +1 (right extension) or -1 (left, reads backwards)
+  int32_t m, n;        // characters available in a and b
+  int32_t X;
+};
+
+template <int CPL>
+struct Tier {
+  static constexpr int Q = 64 * CPL;
+  static constexpr int kNeed = 2 * Q + 66;
+  static constexpr int RING = kNeed <= 256 ? 256
+                              : kNeed <= 512 ? 512
+                              : kNeed <= 1024 ? 1024
+                              : kNeed <= 2048 ? 2048 : 4096;
+  static constexpr int MIR = CPL + 4;      // mirrored slots after the ring
+  static constexpr int LDS_WORDS = RING + MIR;
+};
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+__device__ __forceinline__ uint32_t code_at(const uint32_t* __restrict__ w, int32_t p) {
+  return (w[p >> 4] >> ((p & 15) << 1)) & 3u;
+}
+
+// lane l receives lane l-1's value; lane 0 receives 0
+__device__ __forceinline__ int32_t shr1_zero(int32_t v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
+}
+
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint32_t v) {
+  uint64_t s = v;
+  for (int off = 32; off > 0; off >>= 1) {
+    uint32_t lo = __shfl_xor((uint32_t)s, off, 64);
+    uint32_t hi = __shfl_xor((uint32_t)(s >> 32), off, 64);
+    s += ((uint64_t)hi << 32) | lo;
+  }
+  return s;
+}
+
+__device__ __forceinline__ uint64_t ballot64(bool p) {
+  return __builtin_amdgcn_ballot_w64(p);
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
+// Runs one extension on the calling wavefront.  Returns false on window
+// overflow (res untouched).  ring: LDS_WORDS words private to this wave.
+//
+// UNIT: match == 1.  Then a cell of antidiagonal d scores at most T_{d-1} + 1,
+// so an improving cell is exactly T_{d-1} + 1 and no max-reduction is needed.
+template <int CPL, bool UNIT>
+__device__ bool extend(const Ext& e, const Scoring& sc, uint32_t* __restrict__ ring,
+                       ExtOut& res) {
+  using TI = Tier<CPL>;
+  constexpr int Q = TI::Q;
+  constexpr int RING = TI::RING;
+  constexpr int MASK = RING - 1;
+  constexpr int MIR = TI::MIR;
+  const int lane = lane_id();
+  const int32_t g = __builtin_amdgcn_readfirstlane(-sc.G);
+  const int32_t C = __builtin_amdgcn_readfirstlane(sc.MM + 2 * g);  // mismatch - 2*gap
+  const uint32_t dM = __builtin_amdgcn_readfirstlane((uint32_t)(sc.M - sc.MM));
+  const int32_t bias = __builtin_amdgcn_readfirstlane(e.X + kBias0);
+  const int32_t m = __builtin_amdgcn_readfirstlane(e.m);
+  const int32_t n = __builtin_amdgcn_readfirstlane(e.n);
+
+  int32_t base = 0;
+  int32_t U1[CPL];  // U on the last computed antidiagonal (0 = dead)
+  int32_t Up[CPL];  // U on the one before, shifted up by one cell
+  uint32_t aa[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    U1[c] = (lane == 0 && c == 0) ? bias : 0;  // the origin, U(0,0) = bias
+    Up[c] = 0;
+  }
+  auto load_a = [&]() {
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int32_t i = base + lane * CPL + c;
+      aa[c] = (i >= 1 & i <= m) ? 8u * code_at(e.wa, e.oa + e.dir * (i - 1)) : 0u;
+    }
+  };
+  load_a();
+
+  int32_t filled = -1;  // highest j whose ring slot holds b_j
+  auto fill_to = [&](int32_t jhi) {
+    while (filled < jhi) {
+      const int32_t j = filled + 1 + lane;
+      const uint32_t v =
+          (j >= 1 && j <= n) ? (dM << (8u * code_at(e.wb, e.ob + e.dir * (j - 1)))) : 0u;
+      const int slot = j & MASK;
+      ring[slot] = v;
+      if (slot < MIR) ring[RING + slot] = v;
+      filled += 64;
+    }
+    wave_lds_fence();
+  };
+
+  // live masks per slot: Lc for the last antidiagonal d, Lp for d-1
+  uint64_t Lc[CPL], Lp[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    Lc[c] = (c == 0) ? 1ull : 0ull;
+    Lp[c] = 0ull;
+  }
+  int32_t bi = 0, dstar = 0;  // arg-max row and its antidiagonal
+  int32_t d = 0;
+  // thresholds for antidiagonal d+1, in U units
+  int32_t thr = -e.X + g + bias;  // T_d - X + g*(d+1) + bias
+  int32_t timp = g + bias;        // T_d + g*(d+1) + bias
+  uint32_t cnt = 0;
+  int32_t irow = lane * CPL;  // row of this lane's slot 0 (base + lane*CPL)
+
+  // one antidiagonal; t = position inside the 4-step group, r = ring index
+  // of (slot CPL-1 of this lane) for the group's first antidiagonal
+  auto step = [&](auto masked_tag, int t, int32_t r) {
+    constexpr bool MASKED = decltype(masked_tag)::value;
+    const int32_t dn = d + 1;
+    int32_t upv[CPL];
+    upv[0] = shr1_zero(U1[CPL - 1]);
+#pragma unroll
+    for (int c = 1; c < CPL; ++c) upv[c] = U1[c - 1];
+    uint64_t liveM[CPL], impM[CPL];
+    uint64_t imp_any = 0;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const uint32_t bm = ring[r + t + (CPL - 1 - c)];
+      const int32_t tv = (int32_t)__builtin_amdgcn_ubfe(bm, aa[c], 8);
+      int32_t s = max(max(Up[c] + tv + C, upv[c]), U1[c]);
+      if (MASKED) {
+        const int32_t i = irow + c;
+        const bool out = (i > m) | (i < dn - n);
+        s = out ? 0 : s;
+      }
+      const bool lv = s >= thr;
+      cnt += (s > kEvMin) ? 1u : 0u;
+      liveM[c] = ballot64(lv);
+      impM[c] = ballot64(s > timp);
+      imp_any |= impM[c];
+      Up[c] = upv[c];
+      U1[c] = lv ? s : 0;
+    }
+    if (imp_any) {
+      int32_t dT = 1;
+      uint64_t at[CPL];
+      if (UNIT) {
+        // a cell on dn is at most T_{dn-1} + match: with match 1 every
+        // improving cell holds exactly T + 1
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) at[c] = impM[c];
+      } else {
+        int32_t v = 0;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) v = max(v, U1[c]);
+        const int32_t vmax = __builtin_amdgcn_readfirstlane(wave_max_i32(v));
+        dT = vmax - timp;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) at[c] = ballot64(U1[c] == vmax);
+      }
+      int32_t cell = 0x7fffffff;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c)
+        if (at[c]) cell = min(cell, (int32_t)__builtin_ctzll(at[c]) * CPL + c);
+      thr += dT;
+      timp += dT;
+      bi = base + cell;
+      dstar = dn;
+    }
+    thr += g;
+    timp += g;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      Lp[c] = Lc[c];
+      Lc[c] = liveM[c];
+    }
+    d = dn;
+  };
+
+  bool overflow = false;
+  for (;;) {
+    int32_t lo = Q, hi = -1;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const uint64_t mm = Lc[c] | Lp[c];
+      if (mm) {
+        lo = min(lo, (int32_t)__builtin_ctzll(mm) * CPL + c);
+        hi = max(hi, (63 - (int32_t)__builtin_clzll(mm)) * CPL + c);
+      }
+    }
+    if (hi < 0 || d >= m + n) break;  // two dead antidiagonals, or grid done
+    if (hi + 4 > Q - 1) {
+      const int32_t sl = lo / CPL;  // whole lanes below the band
+      if (sl == 0 || hi - sl * CPL + 4 > Q - 1) {
+        overflow = true;
+        break;
+      }
+      const int src = lane + sl;
+      const bool inside = src < 64;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int32_t u1 = __builtin_amdgcn_ds_bpermute((src & 63) << 2, U1[c]);
+        const int32_t up = __builtin_amdgcn_ds_bpermute((src & 63) << 2, Up[c]);
+        U1[c] = inside ? u1 : 0;
+        Up[c] = inside ? up : 0;
+        Lc[c] >>= sl;
+        Lp[c] >>= sl;
+      }
+      base += sl * CPL;
+      irow += sl * CPL;
+      hi -= sl * CPL;
+      lo -= sl * CPL;
+      load_a();
+    }
+    fill_to(d + 4 - base);
+    // ring index of slot CPL-1 of this lane at antidiagonal d+1
+    const int32_t r = (d + 1 - base - lane * CPL - (CPL - 1)) & MASK;
+    const bool fast = (base + hi + 4 <= m) && (base + lo >= d + 4 - n);
+    if (fast) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) step(std::false_type{}, t, r);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) step(std::true_type{}, t, r);
+    }
+  }
+  if (overflow) return false;
+  const uint64_t cells = wave_sum_u64(cnt);
+  // timp = T + g*(d+1) + bias after the last antidiagonal d
+  res.best = timp - g * (d + 1) - bias;
+  res.bi = bi;
+  res.bj = dstar - bi;
+  res.flags = kExtDone;
+  res.cells = cells;
+  return true;
+}
+
+}  // namespace xd

@@ -1,0 +1,105 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/xdrop.h declares, packs reads in the documented layout and rejects bad
+arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2001_10049_amd as xd
+from paper_2001_10049_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", f)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(xd_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = declared_functions()
+    assert names, "no declarations found"
+    assert names == set(_lib.EXPORTS)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_pack_layout():
+    rng = np.random.default_rng(0)
+    lens = [0, 1, 15, 16, 17, 300, 1000]
+    reads = [rng.integers(0, 4, L, dtype=np.uint8) for L in lens]
+    length = np.array(lens, np.uint32)
+    off = np.concatenate([[0], np.cumsum(length)[:-1]]).astype(np.uint64)
+    codes = np.concatenate(reads)
+    words, woff = xd.pack_reads(codes, off, length)
+    for r, seq in enumerate(reads):
+        assert woff[r] % 16 == 0  # 64-byte aligned reads
+        for u, c in enumerate(seq):
+            w = int(words[int(woff[r]) + u // 16])
+            assert (w >> (2 * (u % 16))) & 3 == c
+        # zero padding after the last base
+        nw = (len(seq) + 15) // 16
+        if len(seq) % 16:
+            tail = int(words[int(woff[r]) + nw - 1]) >> (2 * (len(seq) % 16))
+            assert tail == 0
+    assert len(words) == int(woff[-1]) + ((1000 + 15) // 16 + 15) // 16 * 16
+
+
+def test_pack_rejects_bad_codes():
+    codes = np.array([0, 1, 4], np.uint8)
+    with pytest.raises(xd.XdropError):
+        xd.pack_reads(codes, np.array([0], np.uint64), np.array([3], np.uint32))
+
+
+def test_align_batch_argument_errors_without_device():
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0)
+    args = [None, None, None, 0, 1, 17, 1, -1, -1, None, None, None, None, None, None]
+    # null store
+    assert lib.xd_align_batch(fake, *args) == _lib.XD_EINVAL
+    assert b"store" in lib.xd_last_error()
+
+
+@pytest.mark.parametrize("k,m,mm,g", [(0, 1, -1, -1), (17, 0, -1, -1), (17, 1, 1, -1),
+                                      (17, 1, -1, 0), (17, 200, -1, -1), (17, 1, -1, -200)])
+def test_align_batch_rejects_bad_scoring(k, m, mm, g):
+    lib = _lib.load()
+    dummy = ctypes.c_void_p(1)  # never dereferenced: scalar checks come first
+    rc = lib.xd_align_batch(dummy, None, None, None, 5, 1, k, m, mm, g, None, None, None,
+                            None, None, None)
+    assert rc == _lib.XD_EINVAL
+
+
+def test_align_batch_rejects_bad_scalar_x():
+    lib = _lib.load()
+    dummy = ctypes.c_void_p(1)
+    for x in (-1, _lib.X_MAX + 1):
+        rc = lib.xd_align_batch(dummy, None, None, None, x, 1, 17, 1, -1, -1, None, None,
+                                None, None, None, None)
+        assert rc == _lib.XD_EINVAL
+
+
+def test_store_create_rejects_bad_layout():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    words = np.zeros(4, np.uint32)
+    woff = np.array([0], np.uint64)
+    length = np.array([100], np.uint32)  # needs 7 words, only 4 given
+    rc = lib.xd_store_create(words.ctypes.data_as(ctypes.c_void_p), 4,
+                             woff.ctypes.data_as(ctypes.c_void_p),
+                             length.ctypes.data_as(ctypes.c_void_p), 1, ctypes.byref(h))
+    assert rc == _lib.XD_EINVAL
+    length = np.array([_lib.READ_MAX + 1], np.uint32)
+    rc = lib.xd_store_create(words.ctypes.data_as(ctypes.c_void_p), 4,
+                             woff.ctypes.data_as(ctypes.c_void_p),
+                             length.ctypes.data_as(ctypes.c_void_p), 1, ctypes.byref(h))
+    assert rc == _lib.XD_EINVAL

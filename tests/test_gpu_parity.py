@@ -1,0 +1,184 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Every integer output (score, begin/end coordinates, status, evaluated cells)
+must be identical.  Inputs are seeded synthetic workloads (synth) and
+explicit edge cases.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import mutate_codes, rand_codes, workload_from
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2001_10049_amd as xd  # noqa: E402
+
+
+def run_gpu(w, match=1, mismatch=-1, gap=-1, x=None, x_scalar=0, stream=None):
+    store = xd.ReadStore.from_workload(w)
+    try:
+        pairs, seeds, xs = xd.workload_tensors(w, "cuda")
+        out = xd.align_batch(store, pairs, seeds, x=xs if x is None else x, x_scalar=x_scalar,
+                             k=w.k, match=match, mismatch=mismatch, gap=gap, stream=stream)
+        torch.cuda.synchronize()
+        return {k: v.cpu().numpy() for k, v in out.items()}
+    finally:
+        store.close()
+
+
+def assert_same(got, ref, idx=None, label=""):
+    sel = slice(None) if idx is None else idx
+    for key in ("status", "score"):
+        g, r = got[key][sel], ref[key] if idx is None else ref[key]
+        bad = np.nonzero(g != r)[0]
+        assert bad.size == 0, "%s %s differs at %s: gpu %s oracle %s" % (
+            label, key, bad[:5], g[bad[:5]], r[bad[:5]])
+    for key in ("beg", "end"):
+        g = got[key][sel].astype(np.uint32)
+        r = ref[key]
+        bad = np.nonzero((g != r).any(1))[0]
+        assert bad.size == 0, "%s %s differs at %s: gpu %s oracle %s" % (
+            label, key, bad[:5], g[bad[:5]], r[bad[:5]])
+    g = got["cells"][sel].astype(np.uint64)
+    bad = np.nonzero(g != ref["cells"])[0]
+    assert bad.size == 0, "%s cells differ at %s: gpu %s oracle %s" % (
+        label, bad[:5], g[bad[:5]], ref["cells"][bad[:5]])
+
+
+@pytest.mark.parametrize("name", ["c1", "c1-small", "c2-small", "c3-small", "c4-small"])
+def test_workload_parity(name):
+    print("parity", name, flush=True)
+    w = synth.config(name)
+    got = run_gpu(w)
+    ref = oracle.align_workload(w)
+    assert (ref["status"] == 0).all()
+    assert_same(got, ref, label=name)
+
+
+@pytest.mark.parametrize("scoring", [(2, -3, -2), (1, -2, -1), (3, -1, -2), (5, -4, -1)])
+def test_scoring_variants(scoring):
+    M, MM, G = scoring
+    print("scoring", scoring, flush=True)
+    w = synth.config("c2-small")
+    w = w.subset(np.arange(0, w.n_tasks, 3))
+    got = run_gpu(w, M, MM, G)
+    ref = oracle.align_workload(w, match=M, mismatch=MM, gap=G)
+    assert_same(got, ref, label=str(scoring))
+
+
+@pytest.mark.parametrize("X", [0, 1, 3, 100])
+def test_x_values(X):
+    print("X", X, flush=True)
+    w = synth.config("c2-small")
+    w = w.subset(np.arange(0, w.n_tasks, 5))
+    xs = np.full(w.n_tasks, X, np.int32)
+    w.x = xs
+    got = run_gpu(w)
+    ref = oracle.align_workload(w)
+    assert_same(got, ref, label="X=%d" % X)
+
+
+def test_scalar_x():
+    w = synth.config("c1-small")
+    store = xd.ReadStore.from_workload(w)
+    pairs, seeds, _ = xd.workload_tensors(w, "cuda")
+    out = xd.align_batch(store, pairs, seeds, x=None, x_scalar=11, k=w.k)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    store.close()
+    ref = oracle.align_workload(w, x=np.full(w.n_tasks, 11, np.int32))
+    assert_same(got, ref, label="x_scalar")
+
+
+def edge_workload():
+    rng = np.random.default_rng(7)
+    reads, tasks = [], []
+    A = rand_codes(rng, 3000)
+    reads += [A, A.copy()]                      # 0, 1 identical
+    B = mutate_codes(rng, A, 0.15)
+    reads += [B]                                # 2 noisy copy of A
+    K = rand_codes(rng, 17)
+    reads += [K, K.copy()]                      # 3, 4 reads of length k
+    U = rand_codes(rng, 2500)
+    reads += [U]                                # 5 unrelated
+    C = A[1000:2200].copy()
+    reads += [C]                                # 6 contained in A
+    E = np.concatenate([rand_codes(rng, 500), A[:17]])
+    reads += [E]                                # 7 seed at its end
+    # identical, several X (narrow to wide bands)
+    for X in (0, 1, 7, 25, 50, 200, 600, 1200):
+        tasks.append((0, 1, 1000, 1000, X))
+    # seed at the start / end of both reads
+    tasks += [(0, 1, 0, 0, 25), (0, 1, 3000 - 17, 3000 - 17, 25)]
+    tasks += [(3, 4, 0, 0, 25), (3, 4, 0, 0, 0)]
+    tasks += [(0, 7, 0, 500, 25), (7, 0, 500, 0, 25)]
+    tasks += [(0, 6, 1500, 500, 25), (6, 0, 500, 1500, 40)]
+    # noisy copy: find a shared 17-mer by brute force
+    sa = {bytes(A[i:i + 17]): i for i in range(0, 3000 - 17)}
+    for j in range(0, len(B) - 17):
+        i = sa.get(bytes(B[j:j + 17]))
+        if i is not None and 800 < i < 2200:
+            tasks += [(0, 2, i, j, 7), (0, 2, i, j, 25), (2, 0, j, i, 50), (0, 2, i, j, 300)]
+            break
+    # unrelated reads with a planted shared k-mer: early X-drop exit
+    tasks += [(0, 5, 100, 100, 25)]
+    reads[5][100:117] = A[100:117]
+    # non-exact seed (scored ungapped)
+    tasks += [(0, 5, 2000, 2000, 10)]
+    # invalid tasks
+    tasks += [(0, 99, 0, 0, 25), (99, 0, 0, 0, 25), (0, 1, 2990, 0, 25), (0, 1, 0, 2984, 25),
+              (0, 1, 5, 5, -1), (0, 1, 5, 5, (1 << 20) + 1)]
+    return workload_from(reads, tasks)
+
+
+def test_edge_cases():
+    w = edge_workload()
+    got = run_gpu(w)
+    ref = oracle.align_workload(w)
+    assert_same(got, ref, label="edge")
+
+
+def test_band_overflow_reports_status():
+    # identical 3 kbp reads with a huge X need a band wider than 1024 cells
+    rng = np.random.default_rng(9)
+    A = rand_codes(rng, 3000)
+    w = workload_from([A, A.copy()], [(0, 1, 1500, 1500, 4000), (0, 1, 1500, 1500, 25)])
+    got = run_gpu(w)
+    ref = oracle.align_workload(w)
+    if got["status"][0] == xd.TASK_BAND_OVERFLOW:
+        assert got["score"][0] == np.iinfo(np.int32).min and got["cells"][0] == 0
+        assert_same({k: v[1:] for k, v in got.items()}, {k: v[1:] for k, v in ref.items()})
+    else:
+        assert_same(got, ref, label="wide")
+
+
+def test_empty_batch():
+    w = synth.config("c1-small")
+    store = xd.ReadStore.from_workload(w)
+    e = torch.empty((0, 2), dtype=torch.int32, device="cuda")
+    out = xd.align_batch(store, e, e, x=None, x_scalar=5, k=17)
+    torch.cuda.synchronize()
+    assert out["score"].numel() == 0
+    store.close()
+
+
+def test_repeatable_and_order_independent():
+    w = synth.config("c2-small")
+    a = run_gpu(w)
+    perm = np.random.default_rng(3).permutation(w.n_tasks)
+    b = run_gpu(w.subset(perm))
+    for key in ("score", "status", "beg", "end", "cells"):
+        assert np.array_equal(a[key][perm], b[key]), key
+
+
+def test_store_info():
+    w = synth.config("c1-small")
+    with xd.ReadStore.from_workload(w) as s:
+        info = s.info()
+    assert info["n_reads"] == w.n_reads and info["max_len"] == int(w.length.max())
