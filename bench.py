@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark: X-drop seed-and-extend throughput on one MI355X.
+
+A step is one pass of the whole hot path over one batch: the seed score and
+the left and right X-drop extensions of every task, all tiers and the
+combine kernel (one xd_align_batch call).  The default workload is c2:
+100,000 read pairs from a 30x synthetic 4.6 Mbp read set (log-normal
+lengths, mean 10 kbp, sd 5 kbp, clipped 1-50 kbp; 5/5/5 % errors), one exact
+17-mer seed per pair, X = 25, scores +1/-1/-1.  Inputs are resident in HBM
+before the timed region; the read store upload is not timed.
+
+Prints one JSON line: GCUPS (evaluated cells of both extensions per second,
+the oracle's cell definition) as `value`, pairs/s beside it, the dominant
+kernel's roofline position and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GCUPS and aligned pairs/sec for X-drop extension at X=25 (1 MI355X)"
+# MI355X: 256 CUs x 64 int32 lanes per clock x 2.4 GHz
+PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
+OPS_PER_CELL = 8  # compare, select, add diagonal, max(up,left), add gap, max, compare, select
+DOMINANT = "k_ext_first<1, true>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
+
+WORKLOAD_DESC = {
+    "c2": ("c2: 100,000 read pairs, 4.6 Mbp uniform genome at 30x, read lengths log-normal "
+           "mean 10 kbp sd 5 kbp clipped 1-50 kbp, 5/5/5% sub/ins/del, one exact 17-mer seed "
+           "per pair, X=25, +1/-1/-1"),
+    "c1": ("c1: 1,000 read pairs, 200 kbp genome, reads 2-5 kbp, 5/5/5% errors, X=7, +1/-1/-1"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2001_10049_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch of the dominant kernel from committed counter runs,
+    or None when the kernel sources changed since they were taken."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(w, seconds: float):
+    import numpy as np
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    chunk = 2000
+    done = cells = 0
+    t0 = time.perf_counter()
+    while done < w.n_tasks and time.perf_counter() - t0 < seconds:
+        idx = np.arange(done, min(done + chunk, w.n_tasks))
+        res, used = oracle.align_batch(
+            w.codes, w.off, w.length, np.stack([w.ra[idx], w.rb[idx]], 1),
+            np.stack([w.pa[idx], w.pb[idx]], 1), x=w.x[idx], k=w.k, n_threads=threads)
+        cells += int(res["cells"].sum())
+        done += idx.size
+    dt = time.perf_counter() - t0
+    return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads,
+            "kind": "oracle", "pairs_per_s": round(done / dt, 1),
+            "sample": "first %d tasks of %s (%.1f s wall, %d cells)" % (done, w.name, dt, cells)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_DESC))
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2001_10049_amd as xd
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    log("generating", args.workload)
+    w = synth.config(args.workload)
+    store = xd.ReadStore.from_workload(w)
+    pairs, seeds, x = xd.workload_tensors(w, dev)
+    n = w.n_tasks
+    out = dict(score=torch.empty(n, dtype=torch.int32, device=dev),
+               beg=torch.empty((n, 2), dtype=torch.int32, device=dev),
+               end=torch.empty((n, 2), dtype=torch.int32, device=dev),
+               status=torch.empty(n, dtype=torch.int32, device=dev),
+               cells=torch.empty(n, dtype=torch.int64, device=dev))
+
+    def step():
+        xd.align_batch(store, pairs, seeds, x=x, k=w.k, out=out)
+
+    log("warmup", args.warmup)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if int((out["status"] != 0).sum()) != 0:
+        raise RuntimeError("tasks failed: %s" % np.unique(out["status"].cpu().numpy()))
+    cells_per_step = int(out["cells"].sum())
+
+    xd.profile_enable(True)
+    xd.profile_read(reset=True)
+    log("timing", args.steps, "steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = xd.profile_read(reset=True)
+    xd.profile_enable(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    gcups = cells_per_step / (ms / 1e3) / 1e9
+
+    # dominant kernel: the 64-cell first tier; its algorithmic work is every
+    # cell it completes (all cells when no extension moved to a wider tier)
+    launches = max(prof["batches"], 1)
+    if prof["to_tier2"] == 0:
+        k_ms = prof["ms_tier1"] / launches
+        kernel = DOMINANT
+    else:
+        k_ms = (prof["ms_tier1"] + prof["ms_wide"]) / launches
+        kernel = DOMINANT + " + wide tiers"
+    achieved = OPS_PER_CELL * cells_per_step / (k_ms / 1e3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3),
+                "peak": round(PEAK_INT32_TOPS, 3), "unit": "TOP/s",
+                "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": load_traffic(),
+                "kernel": kernel, "ms_per_launch": round(k_ms, 4),
+                "cells_per_launch": cells_per_step, "ops_per_cell": OPS_PER_CELL,
+                "kernel_gcups": round(cells_per_step / (k_ms / 1e3) / 1e9, 2),
+                "ext_to_wider_tiers": int(prof["to_tier2"])}
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.int32, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle), about %.0f s" % args.cpu_seconds)
+        cpu = cpu_baseline(w, args.cpu_seconds)
+
+    rec = {
+        "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_DESC[args.workload], "pairs": n,
+                   "form": "plain (one xd_align_batch per batch)", "k": w.k},
+        "pairs_per_s": round(n / (ms / 1e3), 1),
+        "cells_per_step": cells_per_step,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    store.close()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

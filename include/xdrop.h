@@ -117,6 +117,27 @@ int xd_align_batch(const xd_store* store, const uint32_t* pairs, const uint32_t*
                    int32_t mismatch, int32_t gap, int32_t* score, uint32_t* beg, uint32_t* end,
                    int32_t* status, uint64_t* cells, void* hip_stream);
 
+/* ---- profiling ----------------------------------------------------------- */
+
+/* Per-kernel timing of the batch pipeline, for benchmarks and roofline
+ * reports.  While enabled (process-wide), every xd_align_batch call records
+ * HIP events on its own stream around each stage and copies the stage's
+ * overflow counts to host memory; xd_profile_read() waits for the recorded
+ * work, sums it into *out and, if reset != 0, forgets it. */
+typedef struct {
+  uint64_t batches;       /* calls recorded */
+  uint64_t extensions;    /* extensions started in the 64-cell tier (2 per task) */
+  uint64_t to_tier2;      /* extensions re-run with the 256-cell window */
+  uint64_t to_tier3;      /* extensions re-run with the 1024-cell window */
+  double ms_tier1;        /* summed kernel time of the 64-cell tier */
+  double ms_wide;         /* summed time of the 256- and 1024-cell tiers */
+  double ms_combine;      /* summed time of the combine kernel */
+  double ms_total;        /* first to last event, summed over calls */
+} xd_profile;
+
+int xd_profile_enable(int on);
+int xd_profile_read(xd_profile* out, int reset);
+
 /* Message for the calling thread's most recent failing call ("" if none). */
 const char* xd_last_error(void);
 

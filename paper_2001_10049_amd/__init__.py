@@ -140,3 +140,15 @@ def workload_tensors(w, device="cuda"):
     seeds = torch.from_numpy(np.stack([w.pa, w.pb], 1).astype(np.int32)).to(device)
     x = torch.from_numpy(w.x.astype(np.int32)).to(device)
     return pairs, seeds, x
+
+
+def profile_enable(on: bool = True) -> None:
+    """Start/stop per-kernel event timing of xd_align_batch calls."""
+    _lib.check(_lib.load().xd_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = True) -> dict:
+    """Waits for recorded batches and returns the summed per-stage profile."""
+    p = _lib.Profile()
+    _lib.check(_lib.load().xd_profile_read(ctypes.byref(p), 1 if reset else 0))
+    return {f: getattr(p, f) for f, _ in _lib.Profile._fields_}

@@ -16,8 +16,16 @@ READ_MAX = 1 << 22
 # every symbol include/xdrop.h declares
 EXPORTS = (
     "xd_pack_reads", "xd_store_create", "xd_store_create_from_codes", "xd_store_destroy",
-    "xd_store_info", "xd_align_batch", "xd_last_error",
+    "xd_store_info", "xd_align_batch", "xd_profile_enable", "xd_profile_read",
+    "xd_last_error",
 )
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_uint64), ("extensions", ctypes.c_uint64),
+                ("to_tier2", ctypes.c_uint64), ("to_tier3", ctypes.c_uint64),
+                ("ms_tier1", ctypes.c_double), ("ms_wide", ctypes.c_double),
+                ("ms_combine", ctypes.c_double), ("ms_total", ctypes.c_double)]
 
 
 class XdropError(RuntimeError):
@@ -53,6 +61,10 @@ def load() -> ctypes.CDLL:
     lib.xd_align_batch.argtypes = [vp, vp, vp, vp, i32, u64, i32, i32, i32, i32, vp, vp, vp,
                                    vp, vp, vp]
     lib.xd_align_batch.restype = ctypes.c_int
+    lib.xd_profile_enable.argtypes = [ctypes.c_int]
+    lib.xd_profile_enable.restype = ctypes.c_int
+    lib.xd_profile_read.argtypes = [ctypes.POINTER(Profile), ctypes.c_int]
+    lib.xd_profile_read.restype = ctypes.c_int
     lib.xd_last_error.argtypes = []
     lib.xd_last_error.restype = ctypes.c_char_p
     _lib = lib

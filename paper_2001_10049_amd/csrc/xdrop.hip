@@ -15,6 +15,8 @@
 #include <stdarg.h>
 #include <string.h>
 
+#include <atomic>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -199,13 +201,15 @@ __global__ __launch_bounds__(256) void k_combine(BatchArgs A) {
 
 template <bool UNIT>
 void launch_extensions(const BatchArgs& A, uint64_t n_ext, uint32_t* list1, uint32_t* list2,
-                       uint32_t* ctr, hipStream_t stream) {
+                       uint32_t* ctr, hipEvent_t* ev, hipStream_t stream) {
   hipLaunchKernelGGL((k_ext_first<1, UNIT>), dim3((uint32_t)n_ext), dim3(64), 0, stream, A,
                      list1, ctr + 0);
+  if (ev) (void)hipEventRecord(ev[1], stream);
   hipLaunchKernelGGL((k_ext_list<4, UNIT, 4>), dim3(kMaxTier2Blocks), dim3(256), 0, stream, A,
                      list1, ctr + 0, ctr + 1, list2, ctr + 2);
   hipLaunchKernelGGL((k_ext_list<16, UNIT, 1>), dim3(kMaxTier2Blocks), dim3(64), 0, stream, A,
                      list2, ctr + 2, ctr + 3, (uint32_t*)nullptr, (uint32_t*)nullptr);
+  if (ev) (void)hipEventRecord(ev[2], stream);
 }
 
 // ---- errors -----------------------------------------------------------------
@@ -244,6 +248,19 @@ int check_scoring(int32_t k, int32_t match, int32_t mismatch, int32_t gap) {
     return fail(XD_EINVAL, "gap must be in [-%d, -1] (got %d)", XD_SCORE_LIMIT, gap);
   return XD_OK;
 }
+
+// ---- profiling records -------------------------------------------------------
+
+struct ProfRecord {
+  hipEvent_t ev[4];     // start, after tier 1, after wide tiers, after combine
+  uint32_t* counters;   // pinned host copy of the overflow counters
+  uint64_t n_ext;
+};
+
+std::atomic<int> g_prof_on{0};
+std::mutex g_prof_mu;
+std::vector<ProfRecord> g_prof_pending;
+xd_profile g_prof_sum = {};
 
 }  // namespace
 
@@ -406,17 +423,63 @@ int xd_align_batch(const xd_store* store, const uint32_t* pairs, const uint32_t*
   uint32_t* list2 = (uint32_t*)(scratch + ext_bytes + list_bytes);
   uint32_t* ctr = (uint32_t*)(scratch + ext_bytes + 2 * list_bytes);
 
+  const bool prof = g_prof_on.load(std::memory_order_relaxed) != 0;
+  ProfRecord rec = {};
+  if (prof) {
+    for (int q = 0; q < 4; ++q) HIP_TRY(hipEventCreate(&rec.ev[q]));
+    HIP_TRY(hipHostMalloc((void**)&rec.counters, 8 * sizeof(uint32_t), hipHostMallocDefault));
+    rec.n_ext = n_ext;
+  }
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, ctr);
+  if (prof) HIP_TRY(hipEventRecord(rec.ev[0], stream));
   if (match == 1) {
-    launch_extensions<true>(A, n_ext, list1, list2, ctr, stream);
+    launch_extensions<true>(A, n_ext, list1, list2, ctr, prof ? rec.ev : nullptr, stream);
   } else {
-    launch_extensions<false>(A, n_ext, list1, list2, ctr, stream);
+    launch_extensions<false>(A, n_ext, list1, list2, ctr, prof ? rec.ev : nullptr, stream);
   }
   hipLaunchKernelGGL(k_combine, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, stream, A);
+  if (prof) {
+    HIP_TRY(hipEventRecord(rec.ev[3], stream));
+    HIP_TRY(hipMemcpyAsync(rec.counters, ctr, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           stream));
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_pending.push_back(rec);
+  }
   hipError_t le = hipGetLastError();
   hipError_t fe = hipFreeAsync(scratch, stream);
   if (le != hipSuccess) return hip_fail(le, "kernel launch");
   if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
+  return XD_OK;
+}
+
+int xd_profile_enable(int on) {
+  g_prof_on.store(on ? 1 : 0);
+  return XD_OK;
+}
+
+int xd_profile_read(xd_profile* out, int reset) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (ProfRecord& r : g_prof_pending) {
+    HIP_TRY(hipEventSynchronize(r.ev[3]));
+    float t1 = 0, t2 = 0, t3 = 0, tt = 0;
+    HIP_TRY(hipEventElapsedTime(&t1, r.ev[0], r.ev[1]));
+    HIP_TRY(hipEventElapsedTime(&t2, r.ev[1], r.ev[2]));
+    HIP_TRY(hipEventElapsedTime(&t3, r.ev[2], r.ev[3]));
+    HIP_TRY(hipEventElapsedTime(&tt, r.ev[0], r.ev[3]));
+    g_prof_sum.batches += 1;
+    g_prof_sum.extensions += r.n_ext;
+    g_prof_sum.to_tier2 += r.counters[0];
+    g_prof_sum.to_tier3 += r.counters[2];
+    g_prof_sum.ms_tier1 += t1;
+    g_prof_sum.ms_wide += t2;
+    g_prof_sum.ms_combine += t3;
+    g_prof_sum.ms_total += tt;
+    for (int q = 0; q < 4; ++q) (void)hipEventDestroy(r.ev[q]);
+    (void)hipHostFree(r.counters);
+  }
+  g_prof_pending.clear();
+  if (out) *out = g_prof_sum;
+  if (reset) g_prof_sum = xd_profile{};
   return XD_OK;
 }
 
