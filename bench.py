@@ -29,7 +29,8 @@ METRIC = "GCUPS and aligned pairs/sec for X-drop extension at X=25 (1 MI355X)"
 # MI355X: 256 CUs x 64 int32 lanes per clock x 2.4 GHz
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
 OPS_PER_CELL = 8  # compare, select, add diagonal, max(up,left), add gap, max, compare, select
-DOMINANT = "k_ext_first<1, true>"
+KERNEL_NAMES = {"plain": "k_ext_first<1, 8, true>",
+                "persistent": "k_ext_list<1, GS, true, 4> (64-cell tier, queue)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
 
 WORKLOAD_DESC = {
@@ -37,6 +38,8 @@ WORKLOAD_DESC = {
            "mean 10 kbp sd 5 kbp clipped 1-50 kbp, 5/5/5% sub/ins/del, one exact 17-mer seed "
            "per pair, X=25, +1/-1/-1"),
     "c1": ("c1: 1,000 read pairs, 200 kbp genome, reads 2-5 kbp, 5/5/5% errors, X=7, +1/-1/-1"),
+    "c3": ("c3: 2,000,000 (pair, seed) tasks over the c2 read set (true seeds >= 17 apart), "
+           "X uniform in {7, 25, 50}, +1/-1/-1"),
 }
 
 
@@ -62,6 +65,16 @@ def load_traffic():
     if t.get("source_hash") != kernel_source_hash():
         return None
     return t.get("bytes_per_launch")
+
+
+def xd_tuned(w):
+    """Tuning for the batched forms: the autotuner's cached choice for this
+    workload shape, else the library defaults."""
+    try:
+        from paper_2001_10049_amd import tune
+        return tune.cached(w) or {}
+    except Exception:
+        return {}
 
 
 def cpu_baseline(w, seconds: float):
@@ -94,6 +107,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for HBM counter scaling)")
+    ap.add_argument("--forms", default="plain,persistent,plan",
+                    help="forms to time; the first one gives `value`")
+    ap.add_argument("--tuning", default="",
+                    help="JSON tuning for the batched forms (default: the tuned cache entry)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -123,40 +140,69 @@ def main():
                status=torch.empty(n, dtype=torch.int32, device=dev),
                cells=torch.empty(n, dtype=torch.int64, device=dev))
 
-    def step():
-        xd.align_batch(store, pairs, seeds, x=x, k=w.k, out=out)
-
-    log("warmup", args.warmup)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    if int((out["status"] != 0).sum()) != 0:
-        raise RuntimeError("tasks failed: %s" % np.unique(out["status"].cpu().numpy()))
-    cells_per_step = int(out["cells"].sum())
-
-    xd.profile_enable(True)
-    xd.profile_read(reset=True)
-    log("timing", args.steps, "steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = xd.profile_read(reset=True)
-    xd.profile_enable(False)
-    ms = (t1 - t0) * 1e3 / args.steps
-    gcups = cells_per_step / (ms / 1e3) / 1e9
+    tuning = json.loads(args.tuning) if args.tuning else xd_tuned(w)
+    forms = [f for f in args.forms.split(",") if f]
+    plan = None
+    if "plan" in forms:
+        plan = xd.Plan(store, pairs, seeds, x=x, k=w.k, out=out, tuning=tuning)
+    steppers = {
+        "plain": lambda: xd.align_batch(store, pairs, seeds, x=x, k=w.k, out=out),
+        "persistent": lambda: xd.align_batch(store, pairs, seeds, x=x, k=w.k, out=out,
+                                             persistent=True, tuning=tuning),
+        "plan": lambda: plan.launch(),
+    }
+    results = {}
+    ref_out = None
+    prof = None
+    for form in forms:
+        step = steppers[form]
+        log("warmup", form, args.warmup)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        if int((out["status"] != 0).sum()) != 0:
+            raise RuntimeError("tasks failed: %s" % np.unique(out["status"].cpu().numpy()))
+        snap = {k: v.clone() for k, v in out.items()}
+        if ref_out is None:
+            ref_out = snap
+        elif not all(torch.equal(ref_out[k], snap[k]) for k in snap):
+            raise RuntimeError("form %s gave different results from %s" % (form, forms[0]))
+        cells_per_step = int(out["cells"].sum())
+        if form != "plan":
+            xd.profile_enable(True)
+            xd.profile_read(reset=True)
+        log("timing", form, args.steps, "steps")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        p = xd.profile_read(reset=True) if form != "plan" else None
+        xd.profile_enable(False)
+        ms_f = (t1 - t0) * 1e3 / args.steps
+        results[form] = {"ms_per_step": round(ms_f, 4),
+                         "gcups": round(cells_per_step / (ms_f / 1e3) / 1e9, 2),
+                         "pairs_per_s": round(n / (ms_f / 1e3), 1)}
+        if p is not None:
+            results[form]["ms_tier1_per_launch"] = round(p["ms_tier1"] / max(p["batches"], 1), 4)
+        if prof is None:
+            prof = p
+    if plan is not None:
+        plan.close()
+    head = forms[0]
+    ms = results[head]["ms_per_step"]
+    gcups = results[head]["gcups"]
 
     # dominant kernel: the 64-cell first tier; its algorithmic work is every
     # cell it completes (all cells when no extension moved to a wider tier)
     launches = max(prof["batches"], 1)
     if prof["to_tier2"] == 0:
         k_ms = prof["ms_tier1"] / launches
-        kernel = DOMINANT
+        kernel = KERNEL_NAMES.get(head, head)
     else:
         k_ms = (prof["ms_tier1"] + prof["ms_wide"]) / launches
-        kernel = DOMINANT + " + wide tiers"
+        kernel = KERNEL_NAMES.get(head, head) + " + wide tiers"
     achieved = OPS_PER_CELL * cells_per_step / (k_ms / 1e3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3),
                 "peak": round(PEAK_INT32_TOPS, 3), "unit": "TOP/s",
@@ -185,8 +231,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_DESC[args.workload], "pairs": n,
-                   "form": "plain (one xd_align_batch per batch)", "k": w.k},
+                   "form": head, "k": w.k, "tuning": tuning},
         "pairs_per_s": round(n / (ms / 1e3), 1),
+        "forms": results,
         "cells_per_step": cells_per_step,
         "roofline": roofline,
         "cpu_baseline": cpu,

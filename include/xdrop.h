@@ -117,6 +117,42 @@ int xd_align_batch(const xd_store* store, const uint32_t* pairs, const uint32_t*
                    int32_t mismatch, int32_t gap, int32_t* score, uint32_t* beg, uint32_t* end,
                    int32_t* status, uint64_t* cells, void* hip_stream);
 
+/* ---- batched form: longest-first device queue, persistent waves ---------- */
+
+/* Tunables of the batched form (all 0 = default).  An autotuner picks them per
+ * workload; results never depend on them. */
+typedef struct {
+  int32_t waves_per_cu; /* resident waves per CU of the persistent kernels: 4..32, default 32 */
+  int32_t group_steps;  /* antidiagonals per group in the 64-cell tier: 4, 8 or 16, default 8 */
+  int32_t order;        /* 1 = longest-first queue (default), 2 = task order */
+  int32_t reserved;
+} xd_tuning;
+
+/* Same contract and results as xd_align_batch.  Extensions are ordered on
+ * the device longest-first (a histogram of estimated antidiagonal counts and
+ * a counting sort) and taken from that queue by persistent wavefronts, so
+ * very uneven task lengths do not leave a long tail.  tuning may be NULL. */
+int xd_align_batch_persistent(const xd_store* store, const uint32_t* pairs,
+                              const uint32_t* seeds, const int32_t* x, int32_t x_scalar,
+                              uint64_t n, int32_t k, int32_t match, int32_t mismatch,
+                              int32_t gap, int32_t* score, uint32_t* beg, uint32_t* end,
+                              int32_t* status, uint64_t* cells, const xd_tuning* tuning,
+                              void* hip_stream);
+
+/* A captured batch: the batched form's kernels recorded once in a hipGraph
+ * for fixed buffers (same meaning as xd_align_batch's) and replayed by
+ * xd_plan_launch.  The plan owns its scratch memory.  Between launches the
+ * caller may rewrite the contents of pairs/seeds/x (same n); the next launch
+ * aligns the new tasks.  xd_plan_destroy waits for the plan's last launch. */
+typedef struct xd_plan xd_plan;
+
+int xd_plan_create(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,
+                   const int32_t* x, int32_t x_scalar, uint64_t n, int32_t k, int32_t match,
+                   int32_t mismatch, int32_t gap, int32_t* score, uint32_t* beg, uint32_t* end,
+                   int32_t* status, uint64_t* cells, const xd_tuning* tuning, xd_plan** out);
+int xd_plan_launch(xd_plan* plan, void* hip_stream);
+void xd_plan_destroy(xd_plan* plan);
+
 /* ---- profiling ----------------------------------------------------------- */
 
 /* Per-kernel timing of the batch pipeline, for benchmarks and roofline

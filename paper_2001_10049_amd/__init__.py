@@ -103,34 +103,94 @@ def _check_dev(name, t, n_items, dtype_bytes):
                          (name, dtype_bytes, n_items))
 
 
-def align_batch(store: ReadStore, pairs, seeds, x=None, x_scalar=0, k=17, match=1,
-                mismatch=-1, gap=-1, out=None, stream=None, with_cells=True):
-    """Aligns n tasks on the GPU (xd_align_batch).
+def _tuning(t):
+    if t is None:
+        return None
+    if isinstance(t, _lib.Tuning):
+        return ctypes.byref(t)
+    s = _lib.Tuning(int(t.get("waves_per_cu", 0)), int(t.get("group_steps", 0)),
+                    int(t.get("order", 0)), 0)
+    return ctypes.byref(s)
 
-    pairs, seeds: int32/uint32 device tensors [n, 2]; x: int32 [n] or None.
-    Returns dict(score int32 [n], beg int32 [n,2], end int32 [n,2],
-    status int32 [n], cells int64 [n]) of device tensors (coordinates hold the
-    uint32 bit patterns).  Asynchronous on `stream` (default: current).
-    """
+
+def _alloc_out(n, dev, with_cells):
     import torch
+    return dict(score=torch.empty(n, dtype=torch.int32, device=dev),
+                beg=torch.empty((n, 2), dtype=torch.int32, device=dev),
+                end=torch.empty((n, 2), dtype=torch.int32, device=dev),
+                status=torch.empty(n, dtype=torch.int32, device=dev),
+                cells=torch.empty(n, dtype=torch.int64, device=dev) if with_cells else None)
+
+
+def _check_batch(pairs, seeds, x, out):
     n = int(pairs.shape[0])
-    dev = pairs.device
     _check_dev("pairs", pairs, 2 * n, 4)
     _check_dev("seeds", seeds, 2 * n, 4)
     if x is not None:
         _check_dev("x", x, n, 4)
     if out is None:
-        out = dict(score=torch.empty(n, dtype=torch.int32, device=dev),
-                   beg=torch.empty((n, 2), dtype=torch.int32, device=dev),
-                   end=torch.empty((n, 2), dtype=torch.int32, device=dev),
-                   status=torch.empty(n, dtype=torch.int32, device=dev),
-                   cells=torch.empty(n, dtype=torch.int64, device=dev) if with_cells else None)
+        out = _alloc_out(n, pairs.device, True)
+    _check_dev("score", out["score"], n, 4)
+    _check_dev("beg", out["beg"], 2 * n, 4)
+    _check_dev("end", out["end"], 2 * n, 4)
+    _check_dev("status", out["status"], n, 4)
+    if out.get("cells") is not None:
+        _check_dev("cells", out["cells"], n, 8)
+    return n, out
+
+
+def align_batch(store: ReadStore, pairs, seeds, x=None, x_scalar=0, k=17, match=1,
+                mismatch=-1, gap=-1, out=None, stream=None, persistent=False, tuning=None):
+    """Aligns n tasks on the GPU (xd_align_batch, or the batched form
+    xd_align_batch_persistent when persistent=True).
+
+    pairs, seeds: int32/uint32 device tensors [n, 2]; x: int32 [n] or None.
+    Returns dict(score int32 [n], beg int32 [n,2], end int32 [n,2],
+    status int32 [n], cells int64 [n]) of device tensors (coordinates hold the
+    uint32 bit patterns).  Asynchronous on `stream` (default: current).
+    tuning: dict(waves_per_cu, group_steps, order) for the batched form.
+    """
+    n, out = _check_batch(pairs, seeds, x, out)
     lib = _lib.load()
-    _lib.check(lib.xd_align_batch(
-        store.handle, _p(pairs), _p(seeds), _p(x), int(x_scalar), n, int(k), int(match),
-        int(mismatch), int(gap), _p(out["score"]), _p(out["beg"]), _p(out["end"]),
-        _p(out["status"]), _p(out.get("cells")), _stream_ptr(stream)))
+    args = (store.handle, _p(pairs), _p(seeds), _p(x), int(x_scalar), n, int(k), int(match),
+            int(mismatch), int(gap), _p(out["score"]), _p(out["beg"]), _p(out["end"]),
+            _p(out["status"]), _p(out.get("cells")))
+    if persistent:
+        _lib.check(lib.xd_align_batch_persistent(*args, _tuning(tuning), _stream_ptr(stream)))
+    else:
+        _lib.check(lib.xd_align_batch(*args, _stream_ptr(stream)))
     return out
+
+
+class Plan:
+    """A captured batch (xd_plan): fixed buffers, replayed with launch()."""
+
+    def __init__(self, store, pairs, seeds, x=None, x_scalar=0, k=17, match=1, mismatch=-1,
+                 gap=-1, out=None, tuning=None):
+        n, out = _check_batch(pairs, seeds, x, out)
+        self.out = out
+        self._keep = (store, pairs, seeds, x)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().xd_plan_create(
+            store.handle, _p(pairs), _p(seeds), _p(x), int(x_scalar), n, int(k), int(match),
+            int(mismatch), int(gap), _p(out["score"]), _p(out["beg"]), _p(out["end"]),
+            _p(out["status"]), _p(out.get("cells")), _tuning(tuning), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _lib.check(_lib.load().xd_plan_launch(self._h, _stream_ptr(stream)))
+        return self.out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.load().xd_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def workload_tensors(w, device="cuda"):

@@ -16,9 +16,15 @@ READ_MAX = 1 << 22
 # every symbol include/xdrop.h declares
 EXPORTS = (
     "xd_pack_reads", "xd_store_create", "xd_store_create_from_codes", "xd_store_destroy",
-    "xd_store_info", "xd_align_batch", "xd_profile_enable", "xd_profile_read",
+    "xd_store_info", "xd_align_batch", "xd_align_batch_persistent", "xd_plan_create",
+    "xd_plan_launch", "xd_plan_destroy", "xd_profile_enable", "xd_profile_read",
     "xd_last_error",
 )
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("waves_per_cu", ctypes.c_int32), ("group_steps", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):
@@ -61,6 +67,15 @@ def load() -> ctypes.CDLL:
     lib.xd_align_batch.argtypes = [vp, vp, vp, vp, i32, u64, i32, i32, i32, i32, vp, vp, vp,
                                    vp, vp, vp]
     lib.xd_align_batch.restype = ctypes.c_int
+    batch = [vp, vp, vp, vp, i32, u64, i32, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.xd_align_batch_persistent.argtypes = batch + [ctypes.POINTER(Tuning), vp]
+    lib.xd_align_batch_persistent.restype = ctypes.c_int
+    lib.xd_plan_create.argtypes = batch + [ctypes.POINTER(Tuning), ctypes.POINTER(vp)]
+    lib.xd_plan_create.restype = ctypes.c_int
+    lib.xd_plan_launch.argtypes = [vp, vp]
+    lib.xd_plan_launch.restype = ctypes.c_int
+    lib.xd_plan_destroy.argtypes = [vp]
+    lib.xd_plan_destroy.restype = None
     lib.xd_profile_enable.argtypes = [ctypes.c_int]
     lib.xd_profile_enable.restype = ctypes.c_int
     lib.xd_profile_read.argtypes = [ctypes.POINTER(Profile), ctypes.c_int]

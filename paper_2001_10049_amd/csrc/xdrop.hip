@@ -1,18 +1,24 @@
 // libxdrop: C ABI for X-drop seed-and-extend on MI355X (declared in
 // include/xdrop.h), with the batch kernels it launches.
 //
-// Batch pipeline (all stream-ordered on the caller's stream):
-//   1. k_reset      zero the overflow-list counters
-//   2. k_ext_first  one wavefront per extension (2 per task: left, right),
-//                   64-cell window; overflowing extensions go to list 1
-//   3. k_ext_list   persistent waves over list 1 with a 256-cell window,
-//                   overflow to list 2; then list 2 with a 1024-cell window
-//   4. k_combine    one thread per task: status, seed score, score,
-//                   coordinates, cells
+// Plain form (xd_align_batch), stream-ordered on the caller's stream:
+//   k_reset      zero the list counters
+//   k_ext_first  one wavefront per extension (2 per task: left, right),
+//                64-cell window; overflowing extensions go to list 1
+//   k_ext_list   persistent waves over list 1 with a 256-cell window,
+//                overflow to list 2; then list 2 with a 1024-cell window
+//   k_combine    one thread per task: status, seed score, score,
+//                coordinates, cells
+//
+// Batched form (xd_align_batch_persistent, xd_plan): k_reset, then
+// k_bin_hist / k_bin_scan / k_bin_scatter build a longest-first queue of
+// extensions (counting sort on an estimated antidiagonal count), persistent
+// waves take the 64-cell tier from that queue, and the wide tiers and the
+// combine follow as above.  A plan records the whole sequence in a hipGraph.
 #include <hip/hip_runtime.h>
+#include <stdarg.h>
 #include <stdint.h>
 #include <stdio.h>
-#include <stdarg.h>
 #include <string.h>
 
 #include <atomic>
@@ -27,7 +33,8 @@ using xd::ExtOut;
 
 namespace {
 
-constexpr uint32_t kMaxTier2Blocks = 2048;
+constexpr uint32_t kWideBlocks = 2048;
+constexpr int kBins = 256;
 
 struct StoreDev {
   const uint32_t* words;
@@ -45,13 +52,45 @@ struct BatchArgs {
   uint32_t n;
   int32_t k;
   xd::Scoring sc;
-  ExtOut* ext;       // [2n]
+  ExtOut* ext;  // [2n]
   int32_t* score;
   uint32_t* beg;
   uint32_t* end;
   int32_t* status;
   uint64_t* cells;
 };
+
+// Device scratch of one batch.
+struct Scratch {
+  ExtOut* ext;        // [2n]
+  uint32_t* queue;    // [2n] extension ids, longest first
+  uint32_t* list1;    // [2n] overflow of the 64-cell tier
+  uint32_t* list2;    // [2n] overflow of the 256-cell tier
+  uint32_t* hist;     // [kBins] histogram, then running cursors
+  uint32_t* ctr;      // [16]: 0 list-1 size, 1 list-1 head, 2 list-2 size,
+                      //       3 list-2 head, 4 queue head
+};
+
+uint64_t scratch_bytes(uint64_t n) {
+  const uint64_t n_ext = 2 * n;
+  const uint64_t ext = (n_ext * sizeof(ExtOut) + 255) & ~255ull;
+  const uint64_t list = (n_ext * 4 + 255) & ~255ull;
+  return ext + 3 * list + kBins * 4 + 256;
+}
+
+Scratch scratch_carve(char* base, uint64_t n) {
+  const uint64_t n_ext = 2 * n;
+  const uint64_t ext = (n_ext * sizeof(ExtOut) + 255) & ~255ull;
+  const uint64_t list = (n_ext * 4 + 255) & ~255ull;
+  Scratch s;
+  s.ext = (ExtOut*)base;
+  s.queue = (uint32_t*)(base + ext);
+  s.list1 = (uint32_t*)(base + ext + list);
+  s.list2 = (uint32_t*)(base + ext + 2 * list);
+  s.hist = (uint32_t*)(base + ext + 3 * list);
+  s.ctr = (uint32_t*)(base + ext + 3 * list + kBins * 4);
+  return s;
+}
 
 // ---- per-task validation (shared by the extension and combine kernels) ----
 __device__ __forceinline__ int32_t task_status(const BatchArgs& A, uint32_t t, uint32_t& ra,
@@ -70,9 +109,22 @@ __device__ __forceinline__ int32_t task_status(const BatchArgs& A, uint32_t t, u
   return XD_TASK_OK;
 }
 
-// Sets up and runs extension e (task e/2; e even = left, odd = right) on the
-// calling wave.  Returns false if it overflowed this tier's window.
-template <int CPL, bool UNIT>
+// Characters available to extension e (even: left of the seed, odd: right).
+__device__ __forceinline__ void ext_lengths(const BatchArgs& A, uint32_t e, uint32_t pa,
+                                            uint32_t pb, int32_t la, int32_t lb, int32_t& m,
+                                            int32_t& n) {
+  if (e & 1) {
+    m = la - (int32_t)pa - A.k;
+    n = lb - (int32_t)pb - A.k;
+  } else {
+    m = (int32_t)pa;
+    n = (int32_t)pb;
+  }
+}
+
+// Sets up and runs extension e on the calling wave.  Returns false if it
+// overflowed this tier's window.
+template <int CPL, int GS, bool UNIT>
 __device__ bool run_ext(const BatchArgs& A, uint32_t e, uint32_t* ring) {
   const uint32_t t = e >> 1;
   uint32_t ra, rb, pa, pb;
@@ -96,21 +148,18 @@ __device__ bool run_ext(const BatchArgs& A, uint32_t e, uint32_t* ring) {
   ex.wa = A.st.words + A.st.word_off[ra];
   ex.wb = A.st.words + A.st.word_off[rb];
   ex.X = X;
+  ext_lengths(A, e, pa, pb, la, lb, ex.m, ex.n);
   if (e & 1) {  // right: suffixes after the seed, forwards
     ex.oa = (int32_t)pa + A.k;
     ex.ob = (int32_t)pb + A.k;
     ex.dir = 1;
-    ex.m = la - ex.oa;
-    ex.n = lb - ex.ob;
   } else {      // left: prefixes before the seed, backwards
     ex.oa = (int32_t)pa - 1;
     ex.ob = (int32_t)pb - 1;
     ex.dir = -1;
-    ex.m = (int32_t)pa;
-    ex.n = (int32_t)pb;
   }
   ExtOut o;
-  if (!xd::extend<CPL, UNIT>(ex, A.sc, ring, o)) return false;
+  if (!xd::extend<CPL, GS, UNIT>(ex, A.sc, ring, o)) return false;
   if (xd::lane_id() == 0) A.ext[e] = o;
   return true;
 }
@@ -122,39 +171,42 @@ __device__ __forceinline__ void push_list(uint32_t* list, uint32_t* count, uint3
   }
 }
 
-// counters: [0] list-1 size, [1] list-1 head, [2] list-2 size, [3] list-2
-// head, [4] list-3 size
-__global__ void k_reset(uint32_t* counters) {
-  if (threadIdx.x < 8) counters[threadIdx.x] = 0;
+// zero the counters and the histogram (a kernel rather than a memset so that
+// graph replays see it as an ordinary node)
+__global__ __launch_bounds__(256) void k_reset(uint32_t* ctr, uint32_t* hist) {
+  if (threadIdx.x < 16) ctr[threadIdx.x] = 0;
+  if (hist) hist[threadIdx.x] = 0;
 }
 
-template <int CPL, bool UNIT>
+template <int CPL, int GS, bool UNIT>
 __global__ __launch_bounds__(64) void k_ext_first(BatchArgs A, uint32_t* ovf_list,
                                                   uint32_t* ovf_count) {
-  __shared__ uint32_t ring[xd::Tier<CPL>::LDS_WORDS];
+  __shared__ uint32_t ring[xd::Tier<CPL, GS>::LDS_WORDS];
   const uint32_t e = blockIdx.x;
-  if (!run_ext<CPL, UNIT>(A, e, ring)) push_list(ovf_list, ovf_count, e);
+  if (!run_ext<CPL, GS, UNIT>(A, e, ring)) push_list(ovf_list, ovf_count, e);
 }
 
-// Persistent waves working through a list of extensions (WAVES waves per
-// block, each with its own ring).
-template <int CPL, bool UNIT, int WAVES>
+// Persistent waves (WAVES per block, each with its own ring) taking
+// extension ids from list[0 .. total) through an atomic head.  total is
+// *count when count is given, else fixed_total.  Overflowing extensions go
+// to ovf_list, or are marked as unresolved when there is no further tier.
+template <int CPL, int GS, bool UNIT, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_ext_list(BatchArgs A, const uint32_t* list,
-                                                         const uint32_t* count, uint32_t* head,
+                                                         const uint32_t* count,
+                                                         uint32_t fixed_total, uint32_t* head,
                                                          uint32_t* ovf_list,
                                                          uint32_t* ovf_count) {
-  static_assert(WAVES * xd::Tier<CPL>::LDS_WORDS * 4 <= 64 * 1024, "LDS per block");
-  __shared__ uint32_t rings[WAVES][xd::Tier<CPL>::LDS_WORDS];
+  static_assert(WAVES * xd::Tier<CPL, GS>::LDS_WORDS * 4 <= 64 * 1024, "LDS per block");
+  __shared__ uint32_t rings[WAVES][xd::Tier<CPL, GS>::LDS_WORDS];
   const int w = threadIdx.x >> 6;
-  const uint32_t total = __builtin_amdgcn_readfirstlane(*count);
+  const uint32_t total = count ? __builtin_amdgcn_readfirstlane(*count) : fixed_total;
   for (;;) {
     uint32_t idx = 0;
     if (xd::lane_id() == 0) idx = atomicAdd(head, 1u);
-    idx = __shfl(idx, 0, 64);
-    idx = __builtin_amdgcn_readfirstlane(idx);
+    idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
     if (idx >= total) break;
-    const uint32_t e = list[idx];
-    if (!run_ext<CPL, UNIT>(A, e, rings[w])) {
+    const uint32_t e = __builtin_amdgcn_readfirstlane(list[idx]);
+    if (!run_ext<CPL, GS, UNIT>(A, e, rings[w])) {
       if (ovf_list) {
         push_list(ovf_list, ovf_count, e);
       } else if (xd::lane_id() == 0) {
@@ -163,6 +215,58 @@ __global__ __launch_bounds__(64 * WAVES) void k_ext_list(BatchArgs A, const uint
       }
     }
   }
+}
+
+// ---- longest-first queue ----------------------------------------------------
+
+// Bin of extension e: 8 bins per octave of the estimated antidiagonal count
+// (a true overlap extends along the diagonal until the shorter side runs
+// out, about 2*min(m, n) antidiagonals).  Invalid tasks go to bin 0.
+__device__ __forceinline__ uint32_t ext_bin(const BatchArgs& A, uint32_t e) {
+  uint32_t ra, rb, pa, pb;
+  int32_t X;
+  if (task_status(A, e >> 1, ra, rb, pa, pb, X) != XD_TASK_OK) return 0;
+  int32_t m, n;
+  ext_lengths(A, e, pa, pb, (int32_t)A.st.len[ra], (int32_t)A.st.len[rb], m, n);
+  const uint32_t cost = 2u * (uint32_t)min(m, n) + 2u;
+  const uint32_t ex = 31u - __builtin_clz(cost);
+  const uint32_t mant = ex >= 3 ? (cost >> (ex - 3)) & 7u : 0u;
+  return min(ex * 8u + mant, (uint32_t)kBins - 1);
+}
+
+__global__ __launch_bounds__(256) void k_bin_hist(BatchArgs A, uint32_t n_ext, uint32_t* hist) {
+  __shared__ uint32_t h[kBins];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+  if (e < n_ext) atomicAdd(&h[ext_bin(A, e)], 1u);
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// hist[b] <- number of extensions in bins above b (queue start of bin b)
+__global__ __launch_bounds__(256) void k_bin_scan(uint32_t* hist) {
+  __shared__ uint32_t h[kBins];
+  const int b = threadIdx.x;
+  h[b] = hist[b];
+  __syncthreads();
+  uint32_t above = 0;
+  for (int q = b + 1; q < kBins; ++q) above += h[q];
+  hist[b] = above;
+}
+
+__global__ __launch_bounds__(256) void k_bin_scatter(BatchArgs A, uint32_t n_ext,
+                                                     uint32_t* cursor, uint32_t* queue) {
+  const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+  if (e >= n_ext) return;
+  const uint32_t pos = atomicAdd(&cursor[ext_bin(A, e)], 1u);
+  queue[pos] = e;
+}
+
+// queue = 0, 1, 2, ... (task order)
+__global__ __launch_bounds__(256) void k_iota(uint32_t n_ext, uint32_t* queue) {
+  const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+  if (e < n_ext) queue[e] = e;
 }
 
 __global__ __launch_bounds__(256) void k_combine(BatchArgs A) {
@@ -199,16 +303,71 @@ __global__ __launch_bounds__(256) void k_combine(BatchArgs A) {
   if (A.cells) A.cells[t] = L.cells + R.cells;
 }
 
+// ---- launch sequences -------------------------------------------------------
+
+// the 256- and 1024-cell tiers over the overflow lists
 template <bool UNIT>
-void launch_extensions(const BatchArgs& A, uint64_t n_ext, uint32_t* list1, uint32_t* list2,
-                       uint32_t* ctr, hipEvent_t* ev, hipStream_t stream) {
-  hipLaunchKernelGGL((k_ext_first<1, UNIT>), dim3((uint32_t)n_ext), dim3(64), 0, stream, A,
-                     list1, ctr + 0);
+void launch_wide(const BatchArgs& A, const Scratch& S, hipStream_t stream) {
+  hipLaunchKernelGGL((k_ext_list<4, 4, UNIT, 4>), dim3(kWideBlocks), dim3(256), 0, stream, A,
+                     S.list1, S.ctr + 0, 0u, S.ctr + 1, S.list2, S.ctr + 2);
+  hipLaunchKernelGGL((k_ext_list<16, 4, UNIT, 1>), dim3(kWideBlocks), dim3(64), 0, stream, A,
+                     S.list2, S.ctr + 2, 0u, S.ctr + 3, (uint32_t*)nullptr,
+                     (uint32_t*)nullptr);
+}
+
+template <bool UNIT>
+void launch_plain_ext(const BatchArgs& A, const Scratch& S, uint64_t n_ext, hipEvent_t* ev,
+                      hipStream_t stream) {
+  hipLaunchKernelGGL((k_ext_first<1, 8, UNIT>), dim3((uint32_t)n_ext), dim3(64), 0, stream, A,
+                     S.list1, S.ctr + 0);
   if (ev) (void)hipEventRecord(ev[1], stream);
-  hipLaunchKernelGGL((k_ext_list<4, UNIT, 4>), dim3(kMaxTier2Blocks), dim3(256), 0, stream, A,
-                     list1, ctr + 0, ctr + 1, list2, ctr + 2);
-  hipLaunchKernelGGL((k_ext_list<16, UNIT, 1>), dim3(kMaxTier2Blocks), dim3(64), 0, stream, A,
-                     list2, ctr + 2, ctr + 3, (uint32_t*)nullptr, (uint32_t*)nullptr);
+  launch_wide<UNIT>(A, S, stream);
+  if (ev) (void)hipEventRecord(ev[2], stream);
+}
+
+struct Tuned {
+  int waves_per_cu, group_steps, order;
+};
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    return 256;
+  return cus;
+}
+
+template <bool UNIT, int GS>
+void launch_queue_tier(const BatchArgs& A, const Scratch& S, uint32_t n_ext, uint32_t blocks,
+                       hipStream_t stream) {
+  hipLaunchKernelGGL((k_ext_list<1, GS, UNIT, 4>), dim3(blocks), dim3(256), 0, stream, A,
+                     S.queue, (const uint32_t*)nullptr, n_ext, S.ctr + 4, S.list1, S.ctr + 0);
+}
+
+template <bool UNIT>
+void launch_persistent_ext(const BatchArgs& A, const Scratch& S, uint64_t n_ext,
+                           const Tuned& tu, hipEvent_t* ev, hipStream_t stream) {
+  const uint32_t grid = (uint32_t)((n_ext + 255) / 256);
+  if (tu.order == 2) {
+    hipLaunchKernelGGL(k_iota, dim3(grid), dim3(256), 0, stream, (uint32_t)n_ext, S.queue);
+  } else {
+    hipLaunchKernelGGL(k_bin_hist, dim3(grid), dim3(256), 0, stream, A, (uint32_t)n_ext, S.hist);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(256), 0, stream, S.hist);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(256), 0, stream, A, (uint32_t)n_ext,
+                       S.hist, S.queue);
+  }
+  if (ev) (void)hipEventRecord(ev[0], stream);
+  uint32_t blocks = (uint32_t)device_cus() * (uint32_t)tu.waves_per_cu / 4u;
+  if (blocks < 1) blocks = 1;
+  if (tu.group_steps == 4)
+    launch_queue_tier<UNIT, 4>(A, S, (uint32_t)n_ext, blocks, stream);
+  else if (tu.group_steps == 16)
+    launch_queue_tier<UNIT, 16>(A, S, (uint32_t)n_ext, blocks, stream);
+  else
+    launch_queue_tier<UNIT, 8>(A, S, (uint32_t)n_ext, blocks, stream);
+  if (ev) (void)hipEventRecord(ev[1], stream);
+  launch_wide<UNIT>(A, S, stream);
   if (ev) (void)hipEventRecord(ev[2], stream);
 }
 
@@ -249,11 +408,33 @@ int check_scoring(int32_t k, int32_t match, int32_t mismatch, int32_t gap) {
   return XD_OK;
 }
 
+int check_tuning(const xd_tuning* t, Tuned& out) {
+  out.waves_per_cu = 32;
+  out.group_steps = 8;
+  out.order = 1;
+  if (!t) return XD_OK;
+  if (t->waves_per_cu) {
+    if (t->waves_per_cu < 4 || t->waves_per_cu > 32 || t->waves_per_cu % 4)
+      return fail(XD_EINVAL, "waves_per_cu must be a multiple of 4 in [4, 32]");
+    out.waves_per_cu = t->waves_per_cu;
+  }
+  if (t->group_steps) {
+    if (t->group_steps != 4 && t->group_steps != 8 && t->group_steps != 16)
+      return fail(XD_EINVAL, "group_steps must be 4, 8 or 16");
+    out.group_steps = t->group_steps;
+  }
+  if (t->order) {
+    if (t->order != 1 && t->order != 2) return fail(XD_EINVAL, "order must be 1 or 2");
+    out.order = t->order;
+  }
+  return XD_OK;
+}
+
 // ---- profiling records -------------------------------------------------------
 
 struct ProfRecord {
-  hipEvent_t ev[4];     // start, after tier 1, after wide tiers, after combine
-  uint32_t* counters;   // pinned host copy of the overflow counters
+  hipEvent_t ev[4];    // start, after tier 1, after wide tiers, after combine
+  uint32_t* counters;  // pinned host copy of the overflow counters
   uint64_t n_ext;
 };
 
@@ -274,6 +455,98 @@ struct xd_store {
   int device = 0;
 };
 
+struct xd_plan {
+  BatchArgs args;
+  Scratch scratch;
+  char* mem = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  int device = 0;
+};
+
+namespace {
+
+int make_args(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,
+              const int32_t* x, int32_t x_scalar, uint64_t n, int32_t k, int32_t match,
+              int32_t mismatch, int32_t gap, int32_t* score, uint32_t* beg, uint32_t* end,
+              int32_t* status, uint64_t* cells, BatchArgs& A) {
+  if (!store) return fail(XD_EINVAL, "store is null");
+  int rc = check_scoring(k, match, mismatch, gap);
+  if (rc) return rc;
+  if (!x && (x_scalar < 0 || x_scalar > XD_X_MAX))
+    return fail(XD_EINVAL, "x_scalar must be in [0, %d] (got %d)", XD_X_MAX, x_scalar);
+  if (n > (1ull << 30)) return fail(XD_EINVAL, "n = %llu exceeds 2^30", (unsigned long long)n);
+  if (n && (!pairs || !seeds || !score || !beg || !end || !status))
+    return fail(XD_EINVAL, "null task or result array");
+  A.st = {store->words, store->word_off, store->len, store->n_reads};
+  A.pairs = pairs;
+  A.seeds = seeds;
+  A.x = x;
+  A.x_scalar = x_scalar;
+  A.n = (uint32_t)n;
+  A.k = k;
+  A.sc = {match, mismatch, gap};
+  A.ext = nullptr;
+  A.score = score;
+  A.beg = beg;
+  A.end = end;
+  A.status = status;
+  A.cells = cells;
+  return XD_OK;
+}
+
+// Enqueues the whole batch on `stream`.  persistent: batched form.
+int enqueue(BatchArgs A, const Scratch& S, bool persistent, const Tuned& tu,
+            hipStream_t stream, bool allow_profile) {
+  A.ext = S.ext;
+  const uint64_t n_ext = 2 * (uint64_t)A.n;
+  const bool prof = allow_profile && g_prof_on.load(std::memory_order_relaxed) != 0;
+  ProfRecord rec = {};
+  if (prof) {
+    for (int q = 0; q < 4; ++q) HIP_TRY(hipEventCreate(&rec.ev[q]));
+    HIP_TRY(hipHostMalloc((void**)&rec.counters, 16 * sizeof(uint32_t), hipHostMallocDefault));
+    rec.n_ext = n_ext;
+  }
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, stream, S.ctr, S.hist);
+  if (persistent) {
+    if (A.sc.M == 1)
+      launch_persistent_ext<true>(A, S, n_ext, tu, prof ? rec.ev : nullptr, stream);
+    else
+      launch_persistent_ext<false>(A, S, n_ext, tu, prof ? rec.ev : nullptr, stream);
+  } else {
+    if (prof) HIP_TRY(hipEventRecord(rec.ev[0], stream));
+    if (A.sc.M == 1)
+      launch_plain_ext<true>(A, S, n_ext, prof ? rec.ev : nullptr, stream);
+    else
+      launch_plain_ext<false>(A, S, n_ext, prof ? rec.ev : nullptr, stream);
+  }
+  hipLaunchKernelGGL(k_combine, dim3((uint32_t)((A.n + 255) / 256)), dim3(256), 0, stream, A);
+  if (prof) {
+    HIP_TRY(hipEventRecord(rec.ev[3], stream));
+    HIP_TRY(hipMemcpyAsync(rec.counters, S.ctr, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           stream));
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_pending.push_back(rec);
+  }
+  hipError_t le = hipGetLastError();
+  if (le != hipSuccess) return hip_fail(le, "kernel launch");
+  return XD_OK;
+}
+
+int batch_async(const BatchArgs& A, bool persistent, const Tuned& tu, hipStream_t stream) {
+  char* mem = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&mem, scratch_bytes(A.n), stream));
+  int rc = enqueue(A, scratch_carve(mem, A.n), persistent, tu, stream, true);
+  hipError_t fe = hipFreeAsync(mem, stream);
+  if (rc) return rc;
+  if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
+  return XD_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* xd_last_error(void) { return g_err.c_str(); }
@@ -293,8 +566,9 @@ int xd_pack_reads(const uint8_t* codes, const uint64_t* off, const uint32_t* len
   }
   if (words) {
     if (!word_off) return fail(XD_EINVAL, "xd_pack_reads: word_off is null");
-    if (pos > *n_words) return fail(XD_EINVAL, "xd_pack_reads: words holds %llu, need %llu",
-                                    (unsigned long long)*n_words, (unsigned long long)pos);
+    if (pos > *n_words)
+      return fail(XD_EINVAL, "xd_pack_reads: words holds %llu, need %llu",
+                  (unsigned long long)*n_words, (unsigned long long)pos);
     memset(words, 0, pos * sizeof(uint32_t));
     for (uint32_t r = 0; r < n_reads; ++r) {
       const uint8_t* c = codes + off[r];
@@ -338,7 +612,8 @@ int xd_store_create(const uint32_t* words, uint64_t n_words, const uint64_t* wor
     e = hipMemcpy(s->words, words, n_words * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess && n_reads)
     e = hipMemcpy(s->word_off, word_off, n_reads * 8ull, hipMemcpyHostToDevice);
-  if (e == hipSuccess && n_reads) e = hipMemcpy(s->len, len, n_reads * 4ull, hipMemcpyHostToDevice);
+  if (e == hipSuccess && n_reads)
+    e = hipMemcpy(s->len, len, n_reads * 4ull, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     int rc = hip_fail(e, "xd_store_create");
     xd_store_destroy(s);
@@ -385,71 +660,99 @@ int xd_align_batch(const xd_store* store, const uint32_t* pairs, const uint32_t*
                    const int32_t* x, int32_t x_scalar, uint64_t n, int32_t k, int32_t match,
                    int32_t mismatch, int32_t gap, int32_t* score, uint32_t* beg, uint32_t* end,
                    int32_t* status, uint64_t* cells, void* hip_stream) {
-  if (!store) return fail(XD_EINVAL, "xd_align_batch: store is null");
-  int rc = check_scoring(k, match, mismatch, gap);
-  if (rc) return rc;
-  if (!x && (x_scalar < 0 || x_scalar > XD_X_MAX))
-    return fail(XD_EINVAL, "x_scalar must be in [0, %d] (got %d)", XD_X_MAX, x_scalar);
-  if (n == 0) return XD_OK;
-  if (n > (1ull << 30)) return fail(XD_EINVAL, "n = %llu exceeds 2^30", (unsigned long long)n);
-  if (!pairs || !seeds || !score || !beg || !end || !status)
-    return fail(XD_EINVAL, "xd_align_batch: null array");
-  hipStream_t stream = (hipStream_t)hip_stream;
-
   BatchArgs A;
-  A.st = {store->words, store->word_off, store->len, store->n_reads};
-  A.pairs = pairs;
-  A.seeds = seeds;
-  A.x = x;
-  A.x_scalar = x_scalar;
-  A.n = (uint32_t)n;
-  A.k = k;
-  A.sc = {match, mismatch, gap};
-  A.score = score;
-  A.beg = beg;
-  A.end = end;
-  A.status = status;
-  A.cells = cells;
+  int rc = make_args(store, pairs, seeds, x, x_scalar, n, k, match, mismatch, gap, score, beg,
+                     end, status, cells, A);
+  if (rc) return rc;
+  if (n == 0) return XD_OK;
+  Tuned tu;
+  check_tuning(nullptr, tu);
+  return batch_async(A, false, tu, (hipStream_t)hip_stream);
+}
 
-  // scratch: extension results, two overflow lists, counters
-  const uint64_t n_ext = 2 * n;
-  const uint64_t ext_bytes = (n_ext * sizeof(ExtOut) + 255) & ~255ull;
-  const uint64_t list_bytes = (n_ext * 4 + 255) & ~255ull;
-  const uint64_t total = ext_bytes + 2 * list_bytes + 256;
-  char* scratch = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&scratch, total, stream));
-  A.ext = (ExtOut*)scratch;
-  uint32_t* list1 = (uint32_t*)(scratch + ext_bytes);
-  uint32_t* list2 = (uint32_t*)(scratch + ext_bytes + list_bytes);
-  uint32_t* ctr = (uint32_t*)(scratch + ext_bytes + 2 * list_bytes);
+int xd_align_batch_persistent(const xd_store* store, const uint32_t* pairs,
+                              const uint32_t* seeds, const int32_t* x, int32_t x_scalar,
+                              uint64_t n, int32_t k, int32_t match, int32_t mismatch,
+                              int32_t gap, int32_t* score, uint32_t* beg, uint32_t* end,
+                              int32_t* status, uint64_t* cells, const xd_tuning* tuning,
+                              void* hip_stream) {
+  BatchArgs A;
+  int rc = make_args(store, pairs, seeds, x, x_scalar, n, k, match, mismatch, gap, score, beg,
+                     end, status, cells, A);
+  if (rc) return rc;
+  Tuned tu;
+  rc = check_tuning(tuning, tu);
+  if (rc) return rc;
+  if (n == 0) return XD_OK;
+  return batch_async(A, true, tu, (hipStream_t)hip_stream);
+}
 
-  const bool prof = g_prof_on.load(std::memory_order_relaxed) != 0;
-  ProfRecord rec = {};
-  if (prof) {
-    for (int q = 0; q < 4; ++q) HIP_TRY(hipEventCreate(&rec.ev[q]));
-    HIP_TRY(hipHostMalloc((void**)&rec.counters, 8 * sizeof(uint32_t), hipHostMallocDefault));
-    rec.n_ext = n_ext;
+int xd_plan_create(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,
+                   const int32_t* x, int32_t x_scalar, uint64_t n, int32_t k, int32_t match,
+                   int32_t mismatch, int32_t gap, int32_t* score, uint32_t* beg, uint32_t* end,
+                   int32_t* status, uint64_t* cells, const xd_tuning* tuning, xd_plan** out) {
+  if (!out) return fail(XD_EINVAL, "xd_plan_create: out is null");
+  *out = nullptr;
+  BatchArgs A;
+  int rc = make_args(store, pairs, seeds, x, x_scalar, n, k, match, mismatch, gap, score, beg,
+                     end, status, cells, A);
+  if (rc) return rc;
+  if (n == 0) return fail(XD_EINVAL, "xd_plan_create: n must be > 0");
+  Tuned tu;
+  rc = check_tuning(tuning, tu);
+  if (rc) return rc;
+  xd_plan* p = new xd_plan();
+  p->args = A;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = hipMalloc((void**)&p->mem, scratch_bytes(n));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    rc = hip_fail(e, "xd_plan_create");
+    xd_plan_destroy(p);
+    return rc;
   }
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, ctr);
-  if (prof) HIP_TRY(hipEventRecord(rec.ev[0], stream));
-  if (match == 1) {
-    launch_extensions<true>(A, n_ext, list1, list2, ctr, prof ? rec.ev : nullptr, stream);
-  } else {
-    launch_extensions<false>(A, n_ext, list1, list2, ctr, prof ? rec.ev : nullptr, stream);
+  p->scratch = scratch_carve(p->mem, n);
+  e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    rc = hip_fail(e, "hipStreamBeginCapture");
+    xd_plan_destroy(p);
+    return rc;
   }
-  hipLaunchKernelGGL(k_combine, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, stream, A);
-  if (prof) {
-    HIP_TRY(hipEventRecord(rec.ev[3], stream));
-    HIP_TRY(hipMemcpyAsync(rec.counters, ctr, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                           stream));
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    g_prof_pending.push_back(rec);
+  rc = enqueue(A, p->scratch, true, tu, p->cap, false);
+  e = hipStreamEndCapture(p->cap, &p->graph);
+  if (rc == XD_OK && e != hipSuccess) rc = hip_fail(e, "hipStreamEndCapture");
+  if (rc == XD_OK) {
+    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) rc = hip_fail(e, "hipGraphInstantiate");
   }
-  hipError_t le = hipGetLastError();
-  hipError_t fe = hipFreeAsync(scratch, stream);
-  if (le != hipSuccess) return hip_fail(le, "kernel launch");
-  if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
+  if (rc) {
+    xd_plan_destroy(p);
+    return rc;
+  }
+  *out = p;
   return XD_OK;
+}
+
+int xd_plan_launch(xd_plan* p, void* hip_stream) {
+  if (!p || !p->exec) return fail(XD_EINVAL, "xd_plan_launch: invalid plan");
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(hipGraphLaunch(p->exec, s));
+  HIP_TRY(hipEventRecord(p->done, s));
+  return XD_OK;
+}
+
+void xd_plan_destroy(xd_plan* p) {
+  if (!p) return;
+  if (p->done) {
+    (void)hipEventSynchronize(p->done);
+    (void)hipEventDestroy(p->done);
+  }
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  if (p->mem) (void)hipFree(p->mem);
+  delete p;
 }
 
 int xd_profile_enable(int on) {

@@ -65,15 +65,15 @@ struct Ext {
   int32_t X;
 };
 
-template <int CPL>
+template <int CPL, int GS>
 struct Tier {
-  static constexpr int Q = 64 * CPL;
-  static constexpr int kNeed = 2 * Q + 66;
+  static constexpr int Q = 64 * CPL;         // window rows
+  static constexpr int kNeed = 2 * Q + 64 + GS + 2;
   static constexpr int RING = kNeed <= 256 ? 256
                               : kNeed <= 512 ? 512
                               : kNeed <= 1024 ? 1024
                               : kNeed <= 2048 ? 2048 : 4096;
-  static constexpr int MIR = CPL + 4;      // mirrored slots after the ring
+  static constexpr int MIR = CPL + GS;       // mirrored slots after the ring
   static constexpr int LDS_WORDS = RING + MIR;
 };
 
@@ -107,6 +107,20 @@ __device__ __forceinline__ uint64_t ballot64(bool p) {
   return __builtin_amdgcn_ballot_w64(p);
 }
 
+// acc + add + (v != 0), on the scalar unit: SCC carries the "nonzero" bit
+// into the add (left to itself the compiler routes that bit through a
+// vector select and a readfirstlane)
+__device__ __forceinline__ int32_t add_nonzero(int32_t acc, int32_t add, uint64_t v) {
+  int32_t r;
+  const int32_t a = __builtin_amdgcn_readfirstlane(acc);
+  const int32_t b = __builtin_amdgcn_readfirstlane(add);
+  asm volatile("s_cmp_lg_u64 %1, 0\n\ts_addc_u32 %0, %2, %3"
+               : "=s"(r)
+               : "s"(v), "s"(a), "s"(b)
+               : "scc");
+  return r;
+}
+
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
@@ -114,12 +128,15 @@ __device__ __forceinline__ void wave_lds_fence() {
 // Runs one extension on the calling wavefront.  Returns false on window
 // overflow (res untouched).  ring: LDS_WORDS words private to this wave.
 //
+// CPL: cells per lane (window of 64*CPL rows).  GS: antidiagonals per group;
+// the window position, the wall test and the ring refill are decided once per
+// group, and the group's ring values are read ahead of its first step.
 // UNIT: match == 1.  Then a cell of antidiagonal d scores at most T_{d-1} + 1,
 // so an improving cell is exactly T_{d-1} + 1 and no max-reduction is needed.
-template <int CPL, bool UNIT>
+template <int CPL, int GS, bool UNIT>
 __device__ bool extend(const Ext& e, const Scoring& sc, uint32_t* __restrict__ ring,
                        ExtOut& res) {
-  using TI = Tier<CPL>;
+  using TI = Tier<CPL, GS>;
   constexpr int Q = TI::Q;
   constexpr int RING = TI::RING;
   constexpr int MASK = RING - 1;
@@ -128,7 +145,8 @@ __device__ bool extend(const Ext& e, const Scoring& sc, uint32_t* __restrict__ r
   const int32_t g = __builtin_amdgcn_readfirstlane(-sc.G);
   const int32_t C = __builtin_amdgcn_readfirstlane(sc.MM + 2 * g);  // mismatch - 2*gap
   const uint32_t dM = __builtin_amdgcn_readfirstlane((uint32_t)(sc.M - sc.MM));
-  const int32_t bias = __builtin_amdgcn_readfirstlane(e.X + kBias0);
+  const int32_t X = __builtin_amdgcn_readfirstlane(e.X);
+  const int32_t bias = X + kBias0;
   const int32_t m = __builtin_amdgcn_readfirstlane(e.m);
   const int32_t n = __builtin_amdgcn_readfirstlane(e.n);
 
@@ -155,7 +173,7 @@ __device__ bool extend(const Ext& e, const Scoring& sc, uint32_t* __restrict__ r
     while (filled < jhi) {
       const int32_t j = filled + 1 + lane;
       const uint32_t v =
-          (j >= 1 && j <= n) ? (dM << (8u * code_at(e.wb, e.ob + e.dir * (j - 1)))) : 0u;
+          (j >= 1 & j <= n) ? (dM << (8u * code_at(e.wb, e.ob + e.dir * (j - 1)))) : 0u;
       const int slot = j & MASK;
       ring[slot] = v;
       if (slot < MIR) ring[RING + slot] = v;
@@ -173,75 +191,91 @@ __device__ bool extend(const Ext& e, const Scoring& sc, uint32_t* __restrict__ r
   }
   int32_t bi = 0, dstar = 0;  // arg-max row and its antidiagonal
   int32_t d = 0;
-  // thresholds for antidiagonal d+1, in U units
-  int32_t thr = -e.X + g + bias;  // T_d - X + g*(d+1) + bias
-  int32_t timp = g + bias;        // T_d + g*(d+1) + bias
-  uint32_t cnt = 0;
-  int32_t irow = lane * CPL;  // row of this lane's slot 0 (base + lane*CPL)
+  // threshold for antidiagonal d+1 in U units: T_d - X + g*(d+1) + bias;
+  // the improvement threshold is thr + X
+  int32_t thr = g + kBias0;
+  uint64_t cnt = 0;  // evaluated cells (wave-uniform)
+  int32_t irow = lane * CPL;  // row of this lane's slot 0 minus base
 
-  // one antidiagonal; t = position inside the 4-step group, r = ring index
-  // of (slot CPL-1 of this lane) for the group's first antidiagonal
-  auto step = [&](auto masked_tag, int t, int32_t r) {
+  // GS antidiagonals d+1 .. d+GS
+  auto group = [&](auto masked_tag) {
     constexpr bool MASKED = decltype(masked_tag)::value;
-    const int32_t dn = d + 1;
-    int32_t upv[CPL];
-    upv[0] = shr1_zero(U1[CPL - 1]);
+    // ring index of slot CPL-1 of this lane at antidiagonal d+1
+    const int32_t r = (d + 1 - base - irow - (CPL - 1)) & MASK;
+    uint32_t bmv[GS][CPL];
 #pragma unroll
-    for (int c = 1; c < CPL; ++c) upv[c] = U1[c - 1];
-    uint64_t liveM[CPL], impM[CPL];
-    uint64_t imp_any = 0;
+    for (int t = 0; t < GS; ++t)
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      const uint32_t bm = ring[r + t + (CPL - 1 - c)];
-      const int32_t tv = (int32_t)__builtin_amdgcn_ubfe(bm, aa[c], 8);
-      int32_t s = max(max(Up[c] + tv + C, upv[c]), U1[c]);
-      if (MASKED) {
-        const int32_t i = irow + c;
-        const bool out = (i > m) | (i < dn - n);
-        s = out ? 0 : s;
+      for (int c = 0; c < CPL; ++c) bmv[t][c] = ring[r + t + (CPL - 1 - c)];
+    uint64_t impM[GS][CPL];
+    uint32_t gcnt = 0;  // evaluated cells in this group (<= GS * 64 * CPL)
+#pragma unroll
+    for (int t = 0; t < GS; ++t) {
+      const int32_t dn = d + 1 + t;
+      const int32_t timp = thr + X;
+      int32_t upv[CPL];
+      upv[0] = shr1_zero(U1[CPL - 1]);
+#pragma unroll
+      for (int c = 1; c < CPL; ++c) upv[c] = U1[c - 1];
+      uint64_t any = 0;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int32_t tv = (int32_t)__builtin_amdgcn_ubfe(bmv[t][c], aa[c], 8);
+        int32_t s = max(max(Up[c] + tv + C, upv[c]), U1[c]);
+        if (MASKED) {
+          const int32_t i = base + irow + c;
+          const bool out = (i > m) | (i < dn - n);
+          s = out ? 0 : s;
+        }
+        const bool lv = s >= thr;
+        gcnt += (uint32_t)__builtin_popcountll(ballot64(s > kEvMin));
+        impM[t][c] = ballot64(s > timp);
+        any |= impM[t][c];
+        if (t >= GS - 2) {
+          Lp[c] = Lc[c];
+          Lc[c] = ballot64(lv);
+        }
+        Up[c] = upv[c];
+        U1[c] = lv ? s : 0;
       }
-      const bool lv = s >= thr;
-      cnt += (s > kEvMin) ? 1u : 0u;
-      liveM[c] = ballot64(lv);
-      impM[c] = ballot64(s > timp);
-      imp_any |= impM[c];
-      Up[c] = upv[c];
-      U1[c] = lv ? s : 0;
-    }
-    if (imp_any) {
-      int32_t dT = 1;
-      uint64_t at[CPL];
       if (UNIT) {
-        // a cell on dn is at most T_{dn-1} + match: with match 1 every
-        // improving cell holds exactly T + 1
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) at[c] = impM[c];
-      } else {
+        thr = add_nonzero(thr, g, any);  // T rises by exactly 1 on improvement
+        continue;
+      }
+      int32_t dT = 0;
+      if (any) {
         int32_t v = 0;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) v = max(v, U1[c]);
         const int32_t vmax = __builtin_amdgcn_readfirstlane(wave_max_i32(v));
         dT = vmax - timp;
+        // the arg-max candidates are the cells holding the new best
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) at[c] = ballot64(U1[c] == vmax);
+        for (int c = 0; c < CPL; ++c) impM[t][c] = ballot64(U1[c] == vmax);
       }
-      int32_t cell = 0x7fffffff;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c)
-        if (at[c]) cell = min(cell, (int32_t)__builtin_ctzll(at[c]) * CPL + c);
-      thr += dT;
-      timp += dT;
-      bi = base + cell;
-      dstar = dn;
+      thr += g + dT;
     }
-    thr += g;
-    timp += g;
+    cnt += gcnt;
+    // arg-max: the last antidiagonal of the group that improved, its
+    // improving cell with the smallest row
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      Lp[c] = Lc[c];
-      Lc[c] = liveM[c];
+    for (int t = GS - 1; t >= 0; --t) {
+      uint64_t any = 0;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) any |= impM[t][c];
+      if (any) {
+        int32_t cell = 0x7fffffff;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          const uint64_t at = impM[t][c];
+          if (at) cell = min(cell, (int32_t)__builtin_ctzll(at) * CPL + c);
+        }
+        bi = base + cell;
+        dstar = d + 1 + t;
+        break;
+      }
     }
-    d = dn;
+    d += GS;
   };
 
   bool overflow = false;
@@ -256,9 +290,9 @@ __device__ bool extend(const Ext& e, const Scoring& sc, uint32_t* __restrict__ r
       }
     }
     if (hi < 0 || d >= m + n) break;  // two dead antidiagonals, or grid done
-    if (hi + 4 > Q - 1) {
+    if (hi + GS > Q - 1) {
       const int32_t sl = lo / CPL;  // whole lanes below the band
-      if (sl == 0 || hi - sl * CPL + 4 > Q - 1) {
+      if (sl == 0 || hi - sl * CPL + GS > Q - 1) {
         overflow = true;
         break;
       }
@@ -274,27 +308,22 @@ __device__ bool extend(const Ext& e, const Scoring& sc, uint32_t* __restrict__ r
         Lp[c] >>= sl;
       }
       base += sl * CPL;
-      irow += sl * CPL;
       hi -= sl * CPL;
       lo -= sl * CPL;
       load_a();
     }
-    fill_to(d + 4 - base);
-    // ring index of slot CPL-1 of this lane at antidiagonal d+1
-    const int32_t r = (d + 1 - base - lane * CPL - (CPL - 1)) & MASK;
-    const bool fast = (base + hi + 4 <= m) && (base + lo >= d + 4 - n);
+    fill_to(d + GS - base);
+    const bool fast = (base + hi + GS <= m) && (base + lo >= d + GS - n);
     if (fast) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) step(std::false_type{}, t, r);
+      group(std::false_type{});
     } else {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) step(std::true_type{}, t, r);
+      group(std::true_type{});
     }
   }
   if (overflow) return false;
-  const uint64_t cells = wave_sum_u64(cnt);
-  // timp = T + g*(d+1) + bias after the last antidiagonal d
-  res.best = timp - g * (d + 1) - bias;
+  const uint64_t cells = cnt;
+  // thr = T - X + g*(d+1) + bias after the last antidiagonal d
+  res.best = thr + X - g * (d + 1) - bias;
   res.bi = bi;
   res.bj = dstar - bi;
   res.flags = kExtDone;

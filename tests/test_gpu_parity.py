@@ -182,3 +182,64 @@ def test_store_info():
     with xd.ReadStore.from_workload(w) as s:
         info = s.info()
     assert info["n_reads"] == w.n_reads and info["max_len"] == int(w.length.max())
+
+
+TUNINGS = [dict(), dict(waves_per_cu=8, group_steps=4), dict(waves_per_cu=16, group_steps=16),
+           dict(order=2, group_steps=8)]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: str(sorted(t.items())))
+@pytest.mark.parametrize("name", ["c2-small", "c3-small", "c4-small"])
+def test_persistent_parity(name, tuning):
+    print("persistent", name, tuning, flush=True)
+    w = synth.config(name)
+    store = xd.ReadStore.from_workload(w)
+    pairs, seeds, x = xd.workload_tensors(w, "cuda")
+    out = xd.align_batch(store, pairs, seeds, x=x, k=w.k, persistent=True, tuning=tuning)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    store.close()
+    assert_same(got, oracle.align_workload(w), label="persistent " + name)
+
+
+def test_persistent_edge_and_scoring():
+    w = edge_workload()
+    store = xd.ReadStore.from_workload(w)
+    pairs, seeds, x = xd.workload_tensors(w, "cuda")
+    for (M, MM, G) in ((1, -1, -1), (2, -3, -2)):
+        out = xd.align_batch(store, pairs, seeds, x=x, k=w.k, match=M, mismatch=MM, gap=G,
+                             persistent=True)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        assert_same(got, oracle.align_workload(w, match=M, mismatch=MM, gap=G),
+                    label="edge persistent %s" % ((M, MM, G),))
+    store.close()
+
+
+def test_plan_replays_and_input_rewrites():
+    w = synth.config("c3-small")
+    ref = oracle.align_workload(w)
+    perm = np.random.default_rng(5).permutation(w.n_tasks)
+    ref_perm = {k: v[perm] for k, v in ref.items()}
+    store = xd.ReadStore.from_workload(w)
+    pairs, seeds, x = xd.workload_tensors(w, "cuda")
+    pairs_p, seeds_p, x_p = xd.workload_tensors(w.subset(perm), "cuda")
+    plan = xd.Plan(store, pairs, seeds, x=x, k=w.k)
+    orig = (pairs.clone(), seeds.clone(), x.clone())
+    for rep in range(4):
+        # eager work and a synchronisation between replays
+        junk = torch.arange(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        if rep % 2:
+            pairs.copy_(pairs_p), seeds.copy_(seeds_p), x.copy_(x_p)
+            expect = ref_perm
+        else:
+            pairs.copy_(orig[0]), seeds.copy_(orig[1]), x.copy_(orig[2])
+            expect = ref
+        out = plan.launch()
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        assert_same(got, expect, label="replay %d" % rep)
+        del junk
+    plan.close()
+    store.close()
