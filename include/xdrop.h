@@ -123,9 +123,12 @@ int xd_align_batch(const xd_store* store, const uint32_t* pairs, const uint32_t*
  * workload; results never depend on them. */
 typedef struct {
   int32_t waves_per_cu; /* resident waves per CU of the persistent kernels: 4..32, default 32 */
-  int32_t group_steps;  /* antidiagonals per group in the 64-cell tier: 4, 8 or 16, default 8 */
+  int32_t group_steps;  /* antidiagonals per group in the 64-cell tier: 4, 8 or 16, default 16 */
   int32_t order;        /* 1 = longest-first queue (default), 2 = task order */
-  int32_t reserved;
+  int32_t x_tier1;      /* tasks with X <= x_tier1 start in the 64-cell window (default 32) */
+  int32_t x_tier2;      /* X <= x_tier2 start in the 128-cell window (default 80); larger X
+                           start in the 256-cell window.  An extension whose band outgrows its
+                           window is re-run in the next wider one (64, 128, 256, 1024). */
 } xd_tuning;
 
 /* Same contract and results as xd_align_batch.  Extensions are ordered on
@@ -163,10 +166,12 @@ void xd_plan_destroy(xd_plan* plan);
 typedef struct {
   uint64_t batches;       /* calls recorded */
   uint64_t extensions;    /* extensions started in the 64-cell tier (2 per task) */
-  uint64_t to_tier2;      /* extensions re-run with the 256-cell window */
-  uint64_t to_tier3;      /* extensions re-run with the 1024-cell window */
-  double ms_tier1;        /* summed kernel time of the 64-cell tier */
-  double ms_wide;         /* summed time of the 256- and 1024-cell tiers */
+  uint64_t to_tier2;      /* extensions moved from the 64- to the 128-cell window */
+  uint64_t to_tier3;      /* moved from the 128- to the 256-cell window */
+  uint64_t to_tier4;      /* moved from the 256- to the 1024-cell window */
+  double ms_tier1;        /* summed time of the 64-cell tier (and, in the batched form,
+                             the queue build before it) */
+  double ms_wide;         /* summed time of the 128-, 256- and 1024-cell tiers */
   double ms_combine;      /* summed time of the combine kernel */
   double ms_total;        /* first to last event, summed over calls */
 } xd_profile;

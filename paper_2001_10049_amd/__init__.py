@@ -109,7 +109,7 @@ def _tuning(t):
     if isinstance(t, _lib.Tuning):
         return ctypes.byref(t)
     s = _lib.Tuning(int(t.get("waves_per_cu", 0)), int(t.get("group_steps", 0)),
-                    int(t.get("order", 0)), 0)
+                    int(t.get("order", 0)), int(t.get("x_tier1", 0)), int(t.get("x_tier2", 0)))
     return ctypes.byref(s)
 
 
@@ -148,7 +148,8 @@ def align_batch(store: ReadStore, pairs, seeds, x=None, x_scalar=0, k=17, match=
     Returns dict(score int32 [n], beg int32 [n,2], end int32 [n,2],
     status int32 [n], cells int64 [n]) of device tensors (coordinates hold the
     uint32 bit patterns).  Asynchronous on `stream` (default: current).
-    tuning: dict(waves_per_cu, group_steps, order) for the batched form.
+    tuning: dict(waves_per_cu, group_steps, order, x_tier1, x_tier2) for the
+    batched form (see xd_tuning).
     """
     n, out = _check_batch(pairs, seeds, x, out)
     lib = _lib.load()

@@ -24,12 +24,14 @@ EXPORTS = (
 
 class Tuning(ctypes.Structure):
     _fields_ = [("waves_per_cu", ctypes.c_int32), ("group_steps", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("x_tier1", ctypes.c_int32),
+                ("x_tier2", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_uint64), ("extensions", ctypes.c_uint64),
                 ("to_tier2", ctypes.c_uint64), ("to_tier3", ctypes.c_uint64),
+                ("to_tier4", ctypes.c_uint64),
                 ("ms_tier1", ctypes.c_double), ("ms_wide", ctypes.c_double),
                 ("ms_combine", ctypes.c_double), ("ms_total", ctypes.c_double)]
 

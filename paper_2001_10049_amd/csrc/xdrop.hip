@@ -1,20 +1,24 @@
 // libxdrop: C ABI for X-drop seed-and-extend on MI355X (declared in
 // include/xdrop.h), with the batch kernels it launches.
 //
+// Windows ("tiers") of 64, 128, 256 and 1024 cells; an extension whose band
+// outgrows its window is appended to the next tier's overflow list and re-run
+// there from the start.
+//
 // Plain form (xd_align_batch), stream-ordered on the caller's stream:
-//   k_reset      zero the list counters
-//   k_ext_first  one wavefront per extension (2 per task: left, right),
-//                64-cell window; overflowing extensions go to list 1
-//   k_ext_list   persistent waves over list 1 with a 256-cell window,
-//                overflow to list 2; then list 2 with a 1024-cell window
+//   k_reset      zero the counters and the histogram
+//   k_ext_first  one wavefront per extension (2 per task: left, right) with
+//                the 64-cell window
+//   k_ext_tier   persistent waves over the overflow lists of the wider tiers
 //   k_combine    one thread per task: status, seed score, score,
 //                coordinates, cells
 //
 // Batched form (xd_align_batch_persistent, xd_plan): k_reset, then
-// k_bin_hist / k_bin_scan / k_bin_scatter build a longest-first queue of
-// extensions (counting sort on an estimated antidiagonal count), persistent
-// waves take the 64-cell tier from that queue, and the wide tiers and the
-// combine follow as above.  A plan records the whole sequence in a hipGraph.
+// k_bin_hist / k_bin_scan / k_bin_scatter sort the extensions on the device
+// by first tier (chosen from X) and, within a tier, longest first (counting
+// sort on an estimated antidiagonal count).  Each tier's persistent waves
+// take its queue segment and then the previous tier's overflow list; the
+// combine follows.  A plan records the whole sequence in a hipGraph.
 #include <hip/hip_runtime.h>
 #include <stdarg.h>
 #include <stdint.h>
@@ -34,7 +38,8 @@ using xd::ExtOut;
 namespace {
 
 constexpr uint32_t kWideBlocks = 2048;
-constexpr int kBins = 256;
+constexpr int kCostBins = 128;          // per tier
+constexpr int kBins = 4 * kCostBins;    // tier-major
 
 struct StoreDev {
   const uint32_t* words;
@@ -63,19 +68,24 @@ struct BatchArgs {
 // Device scratch of one batch.
 struct Scratch {
   ExtOut* ext;        // [2n]
-  uint32_t* queue;    // [2n] extension ids, longest first
-  uint32_t* list1;    // [2n] overflow of the 64-cell tier
-  uint32_t* list2;    // [2n] overflow of the 256-cell tier
+  uint32_t* queue;    // [2n] extension ids: tier-major, longest first
+  uint32_t* ovf[3];   // [2n] each: overflow of tier t into tier t+1
   uint32_t* hist;     // [kBins] histogram, then running cursors
-  uint32_t* ctr;      // [16]: 0 list-1 size, 1 list-1 head, 2 list-2 size,
-                      //       3 list-2 head, 4 queue head
+  uint32_t* ctr;      // [32] counters, see below
+  void* targs;        // [4] TierArgs of the four tiers
 };
+// ctr layout
+constexpr int kOvfCount = 0;   // [0..2] sizes of ovf[0..2]
+constexpr int kHead = 4;       // [4..7] work heads of tiers 0..3
+constexpr int kSeg = 8;        // [8..12] queue start of tiers 0..3, then 2n
+constexpr int kCtrWords = 32;
+constexpr int kTierArgsBytes = 4 * 256;  // >= 4 * sizeof(TierArgs), checked below
 
 uint64_t scratch_bytes(uint64_t n) {
   const uint64_t n_ext = 2 * n;
   const uint64_t ext = (n_ext * sizeof(ExtOut) + 255) & ~255ull;
   const uint64_t list = (n_ext * 4 + 255) & ~255ull;
-  return ext + 3 * list + kBins * 4 + 256;
+  return ext + 4 * list + kBins * 4 + kCtrWords * 4 + kTierArgsBytes;
 }
 
 Scratch scratch_carve(char* base, uint64_t n) {
@@ -85,12 +95,31 @@ Scratch scratch_carve(char* base, uint64_t n) {
   Scratch s;
   s.ext = (ExtOut*)base;
   s.queue = (uint32_t*)(base + ext);
-  s.list1 = (uint32_t*)(base + ext + list);
-  s.list2 = (uint32_t*)(base + ext + 2 * list);
-  s.hist = (uint32_t*)(base + ext + 3 * list);
-  s.ctr = (uint32_t*)(base + ext + 3 * list + kBins * 4);
+  for (int q = 0; q < 3; ++q) s.ovf[q] = (uint32_t*)(base + ext + (1 + q) * list);
+  s.hist = (uint32_t*)(base + ext + 4 * list);
+  s.ctr = (uint32_t*)(base + ext + 4 * list + kBins * 4);
+  s.targs = base + ext + 4 * list + kBins * 4 + kCtrWords * 4;
   return s;
 }
+
+// Arguments of a persistent tier.
+struct TierArgs {
+  BatchArgs A;
+  const uint32_t* queue;
+  const uint32_t* seg;      // [2]: this tier's queue segment, or null
+  const uint32_t* in_list;  // overflow of the previous tier, or null
+  const uint32_t* in_count;
+  uint32_t* head;
+  uint32_t* out_list;       // overflow into the next tier, or null
+  uint32_t* out_count;
+};
+
+static_assert(4 * sizeof(TierArgs) <= kTierArgsBytes, "tier argument area");
+static_assert(sizeof(TierArgs) % 4 == 0, "tier arguments copied by words");
+
+struct TierPack {
+  TierArgs t[4];
+};
 
 // ---- per-task validation (shared by the extension and combine kernels) ----
 __device__ __forceinline__ int32_t task_status(const BatchArgs& A, uint32_t t, uint32_t& ra,
@@ -125,7 +154,7 @@ __device__ __forceinline__ void ext_lengths(const BatchArgs& A, uint32_t e, uint
 // Sets up and runs extension e on the calling wave.  Returns false if it
 // overflowed this tier's window.
 template <int CPL, int GS, bool UNIT>
-__device__ bool run_ext(const BatchArgs& A, uint32_t e, uint32_t* ring) {
+__device__ __forceinline__ bool run_ext(const BatchArgs& A, uint32_t e, uint32_t* ring) {
   const uint32_t t = e >> 1;
   uint32_t ra, rb, pa, pb;
   int32_t X;
@@ -173,9 +202,13 @@ __device__ __forceinline__ void push_list(uint32_t* list, uint32_t* count, uint3
 
 // zero the counters and the histogram (a kernel rather than a memset so that
 // graph replays see it as an ordinary node)
-__global__ __launch_bounds__(256) void k_reset(uint32_t* ctr, uint32_t* hist) {
-  if (threadIdx.x < 16) ctr[threadIdx.x] = 0;
-  if (hist) hist[threadIdx.x] = 0;
+// and store the tier arguments where the tier kernels re-read them
+__global__ __launch_bounds__(256) void k_reset(uint32_t* ctr, uint32_t* hist, TierPack pack,
+                                               uint32_t* targs) {
+  if (threadIdx.x < kCtrWords) ctr[threadIdx.x] = 0;
+  for (int b = threadIdx.x; b < kBins; b += 256) hist[b] = 0;
+  const uint32_t* src = (const uint32_t*)&pack;
+  for (int q = threadIdx.x; q < (int)(sizeof(TierPack) / 4); q += 256) targs[q] = src[q];
 }
 
 template <int CPL, int GS, bool UNIT>
@@ -186,87 +219,105 @@ __global__ __launch_bounds__(64) void k_ext_first(BatchArgs A, uint32_t* ovf_lis
   if (!run_ext<CPL, GS, UNIT>(A, e, ring)) push_list(ovf_list, ovf_count, e);
 }
 
-// Persistent waves (WAVES per block, each with its own ring) taking
-// extension ids from list[0 .. total) through an atomic head.  total is
-// *count when count is given, else fixed_total.  Overflowing extensions go
-// to ovf_list, or are marked as unresolved when there is no further tier.
+// Persistent waves (WAVES per block, each with its own ring).  Work item idx
+// (taken through an atomic head) is queue[seg[0] + idx] for idx below the
+// segment length seg[1] - seg[0], then in_list[idx - segment length] for the
+// in_count extensions that overflowed the previous tier.  Overflowing
+// extensions go to out_list, or are marked unresolved when there is no
+// wider tier.
 template <int CPL, int GS, bool UNIT, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_ext_list(BatchArgs A, const uint32_t* list,
-                                                         const uint32_t* count,
-                                                         uint32_t fixed_total, uint32_t* head,
-                                                         uint32_t* ovf_list,
-                                                         uint32_t* ovf_count) {
+__global__ __launch_bounds__(64 * WAVES) void k_ext_tier(const TierArgs* __restrict__ P) {
   static_assert(WAVES * xd::Tier<CPL, GS>::LDS_WORDS * 4 <= 64 * 1024, "LDS per block");
   __shared__ uint32_t rings[WAVES][xd::Tier<CPL, GS>::LDS_WORDS];
   const int w = threadIdx.x >> 6;
-  const uint32_t total = count ? __builtin_amdgcn_readfirstlane(*count) : fixed_total;
+  const TierArgs* pp = P;
   for (;;) {
+    // the arguments are re-read (scalar loads) after every extension instead
+    // of being held in scalar registers through the extension's loop
+    asm volatile("" : "+s"(pp));
+    const TierArgs& Q = *pp;
+    const uint32_t seg_lo = Q.seg ? __builtin_amdgcn_readfirstlane(Q.seg[0]) : 0u;
+    const uint32_t seg_len = Q.seg ? __builtin_amdgcn_readfirstlane(Q.seg[1]) - seg_lo : 0u;
+    const uint32_t n_in = Q.in_count ? __builtin_amdgcn_readfirstlane(*Q.in_count) : 0u;
     uint32_t idx = 0;
-    if (xd::lane_id() == 0) idx = atomicAdd(head, 1u);
+    if (xd::lane_id() == 0) idx = atomicAdd(Q.head, 1u);
     idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
-    if (idx >= total) break;
-    const uint32_t e = __builtin_amdgcn_readfirstlane(list[idx]);
-    if (!run_ext<CPL, GS, UNIT>(A, e, rings[w])) {
-      if (ovf_list) {
-        push_list(ovf_list, ovf_count, e);
+    if (idx >= seg_len + n_in) break;
+    const uint32_t e = __builtin_amdgcn_readfirstlane(
+        idx < seg_len ? Q.queue[seg_lo + idx] : Q.in_list[idx - seg_len]);
+    if (!run_ext<CPL, GS, UNIT>(Q.A, e, rings[w])) {
+      const TierArgs& R = *pp;
+      if (R.out_list) {
+        push_list(R.out_list, R.out_count, e);
       } else if (xd::lane_id() == 0) {
         ExtOut o = {0, 0, 0, xd::kExtOverflow, 0};
-        A.ext[e] = o;
+        R.A.ext[e] = o;
       }
     }
   }
 }
 
-// ---- longest-first queue ----------------------------------------------------
+// ---- queue: tier-major, longest first ------------------------------------
 
-// Bin of extension e: 8 bins per octave of the estimated antidiagonal count
-// (a true overlap extends along the diagonal until the shorter side runs
-// out, about 2*min(m, n) antidiagonals).  Invalid tasks go to bin 0.
-__device__ __forceinline__ uint32_t ext_bin(const BatchArgs& A, uint32_t e) {
+struct BinRule {
+  int32_t x_tier1, x_tier2;  // X limits of the 64- and 128-cell first tiers
+  int32_t by_cost;           // 0: keep task order inside a tier
+};
+
+// Sort key of extension e, ascending = processing order: first tier from X,
+// then 8 bins per octave of the estimated antidiagonal count (a true overlap
+// extends along the diagonal until the shorter side runs out, about
+// 2*min(m, n) antidiagonals), longest first.  Invalid tasks sort last.
+__device__ __forceinline__ uint32_t ext_key(const BatchArgs& A, const BinRule& R, uint32_t e) {
   uint32_t ra, rb, pa, pb;
   int32_t X;
-  if (task_status(A, e >> 1, ra, rb, pa, pb, X) != XD_TASK_OK) return 0;
+  if (task_status(A, e >> 1, ra, rb, pa, pb, X) != XD_TASK_OK) return kBins - 1;
+  const uint32_t tier = X <= R.x_tier1 ? 0u : X <= R.x_tier2 ? 1u : 2u;
+  if (!R.by_cost) return tier * kCostBins;
   int32_t m, n;
   ext_lengths(A, e, pa, pb, (int32_t)A.st.len[ra], (int32_t)A.st.len[rb], m, n);
   const uint32_t cost = 2u * (uint32_t)min(m, n) + 2u;
   const uint32_t ex = 31u - __builtin_clz(cost);
   const uint32_t mant = ex >= 3 ? (cost >> (ex - 3)) & 7u : 0u;
-  return min(ex * 8u + mant, (uint32_t)kBins - 1);
+  const uint32_t cb = min(ex * 8u + mant, (uint32_t)kCostBins - 1);
+  return tier * kCostBins + (kCostBins - 1 - cb);
 }
 
-__global__ __launch_bounds__(256) void k_bin_hist(BatchArgs A, uint32_t n_ext, uint32_t* hist) {
+__global__ __launch_bounds__(256) void k_bin_hist(BatchArgs A, BinRule R, uint32_t n_ext,
+                                                  uint32_t* hist) {
   __shared__ uint32_t h[kBins];
-  h[threadIdx.x] = 0;
+  for (int b = threadIdx.x; b < kBins; b += 256) h[b] = 0;
   __syncthreads();
   const uint32_t e = blockIdx.x * 256u + threadIdx.x;
-  if (e < n_ext) atomicAdd(&h[ext_bin(A, e)], 1u);
+  if (e < n_ext) atomicAdd(&h[ext_key(A, R, e)], 1u);
   __syncthreads();
-  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+  for (int b = threadIdx.x; b < kBins; b += 256)
+    if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
-// hist[b] <- number of extensions in bins above b (queue start of bin b)
-__global__ __launch_bounds__(256) void k_bin_scan(uint32_t* hist) {
+// hist[b] <- number of extensions with a smaller key (queue start of key b);
+// seg[t] <- queue start of tier t (seg[3] also covers the invalid tasks),
+// seg[4] = n_ext
+__global__ __launch_bounds__(256) void k_bin_scan(uint32_t* hist, uint32_t* seg,
+                                                  uint32_t n_ext) {
   __shared__ uint32_t h[kBins];
-  const int b = threadIdx.x;
-  h[b] = hist[b];
+  for (int b = threadIdx.x; b < kBins; b += 256) h[b] = hist[b];
   __syncthreads();
-  uint32_t above = 0;
-  for (int q = b + 1; q < kBins; ++q) above += h[q];
-  hist[b] = above;
+  for (int b = threadIdx.x; b < kBins; b += 256) {
+    uint32_t below = 0;
+    for (int q = 0; q < b; ++q) below += h[q];
+    hist[b] = below;
+    if (b % kCostBins == 0) seg[b / kCostBins] = below;
+  }
+  if (threadIdx.x == 0) seg[4] = n_ext;
 }
 
-__global__ __launch_bounds__(256) void k_bin_scatter(BatchArgs A, uint32_t n_ext,
+__global__ __launch_bounds__(256) void k_bin_scatter(BatchArgs A, BinRule R, uint32_t n_ext,
                                                      uint32_t* cursor, uint32_t* queue) {
   const uint32_t e = blockIdx.x * 256u + threadIdx.x;
   if (e >= n_ext) return;
-  const uint32_t pos = atomicAdd(&cursor[ext_bin(A, e)], 1u);
+  const uint32_t pos = atomicAdd(&cursor[ext_key(A, R, e)], 1u);
   queue[pos] = e;
-}
-
-// queue = 0, 1, 2, ... (task order)
-__global__ __launch_bounds__(256) void k_iota(uint32_t n_ext, uint32_t* queue) {
-  const uint32_t e = blockIdx.x * 256u + threadIdx.x;
-  if (e < n_ext) queue[e] = e;
 }
 
 __global__ __launch_bounds__(256) void k_combine(BatchArgs A) {
@@ -305,28 +356,8 @@ __global__ __launch_bounds__(256) void k_combine(BatchArgs A) {
 
 // ---- launch sequences -------------------------------------------------------
 
-// the 256- and 1024-cell tiers over the overflow lists
-template <bool UNIT>
-void launch_wide(const BatchArgs& A, const Scratch& S, hipStream_t stream) {
-  hipLaunchKernelGGL((k_ext_list<4, 4, UNIT, 4>), dim3(kWideBlocks), dim3(256), 0, stream, A,
-                     S.list1, S.ctr + 0, 0u, S.ctr + 1, S.list2, S.ctr + 2);
-  hipLaunchKernelGGL((k_ext_list<16, 4, UNIT, 1>), dim3(kWideBlocks), dim3(64), 0, stream, A,
-                     S.list2, S.ctr + 2, 0u, S.ctr + 3, (uint32_t*)nullptr,
-                     (uint32_t*)nullptr);
-}
-
-template <bool UNIT>
-void launch_plain_ext(const BatchArgs& A, const Scratch& S, uint64_t n_ext, hipEvent_t* ev,
-                      hipStream_t stream) {
-  hipLaunchKernelGGL((k_ext_first<1, 8, UNIT>), dim3((uint32_t)n_ext), dim3(64), 0, stream, A,
-                     S.list1, S.ctr + 0);
-  if (ev) (void)hipEventRecord(ev[1], stream);
-  launch_wide<UNIT>(A, S, stream);
-  if (ev) (void)hipEventRecord(ev[2], stream);
-}
-
 struct Tuned {
-  int waves_per_cu, group_steps, order;
+  int waves_per_cu, group_steps, order, x_tier1, x_tier2;
 };
 
 int device_cus() {
@@ -338,36 +369,70 @@ int device_cus() {
   return cus;
 }
 
+// tiers 1..3 (128, 256, 1024 cells): queue segments (batched form only) and
+// overflow lists of the tier below
+// tier arguments: tier 0 (64 cells, batched form) and tiers 1..3 (128, 256,
+// 1024 cells) with their queue segments (batched form) and overflow lists
+TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
+  uint32_t* c = S.ctr;
+  TierPack p;
+  p.t[0] = {A, S.queue, c + kSeg + 0, nullptr, nullptr, c + kHead + 0, S.ovf[0],
+            c + kOvfCount + 0};
+  p.t[1] = {A, S.queue, segs ? c + kSeg + 1 : nullptr, S.ovf[0], c + kOvfCount + 0,
+            c + kHead + 1, S.ovf[1], c + kOvfCount + 1};
+  p.t[2] = {A, S.queue, segs ? c + kSeg + 2 : nullptr, S.ovf[1], c + kOvfCount + 1,
+            c + kHead + 2, S.ovf[2], c + kOvfCount + 2};
+  p.t[3] = {A, S.queue, segs ? c + kSeg + 3 : nullptr, S.ovf[2], c + kOvfCount + 2,
+            c + kHead + 3, nullptr, nullptr};
+  return p;
+}
+
+template <bool UNIT>
+void launch_wide(const Scratch& S, uint32_t blocks, hipStream_t stream) {
+  const TierArgs* ta = (const TierArgs*)S.targs;
+  hipLaunchKernelGGL((k_ext_tier<2, 8, UNIT, 4>), dim3(blocks), dim3(256), 0, stream, ta + 1);
+  hipLaunchKernelGGL((k_ext_tier<4, 4, UNIT, 4>), dim3(blocks), dim3(256), 0, stream, ta + 2);
+  hipLaunchKernelGGL((k_ext_tier<16, 2, UNIT, 1>), dim3(4 * blocks), dim3(64), 0, stream,
+                     ta + 3);
+}
+
+template <bool UNIT>
+void launch_plain_ext(const BatchArgs& A, const Scratch& S, uint64_t n_ext, hipEvent_t* ev,
+                      hipStream_t stream) {
+  hipLaunchKernelGGL((k_ext_first<1, 16, UNIT>), dim3((uint32_t)n_ext), dim3(64), 0, stream, A,
+                     S.ovf[0], S.ctr + kOvfCount + 0);
+  if (ev) (void)hipEventRecord(ev[1], stream);
+  launch_wide<UNIT>(S, kWideBlocks / 4, stream);
+  if (ev) (void)hipEventRecord(ev[2], stream);
+}
+
 template <bool UNIT, int GS>
-void launch_queue_tier(const BatchArgs& A, const Scratch& S, uint32_t n_ext, uint32_t blocks,
-                       hipStream_t stream) {
-  hipLaunchKernelGGL((k_ext_list<1, GS, UNIT, 4>), dim3(blocks), dim3(256), 0, stream, A,
-                     S.queue, (const uint32_t*)nullptr, n_ext, S.ctr + 4, S.list1, S.ctr + 0);
+void launch_tier0(const Scratch& S, uint32_t blocks, hipStream_t stream) {
+  hipLaunchKernelGGL((k_ext_tier<1, GS, UNIT, 4>), dim3(blocks), dim3(256), 0, stream,
+                     (const TierArgs*)S.targs);
 }
 
 template <bool UNIT>
 void launch_persistent_ext(const BatchArgs& A, const Scratch& S, uint64_t n_ext,
                            const Tuned& tu, hipEvent_t* ev, hipStream_t stream) {
   const uint32_t grid = (uint32_t)((n_ext + 255) / 256);
-  if (tu.order == 2) {
-    hipLaunchKernelGGL(k_iota, dim3(grid), dim3(256), 0, stream, (uint32_t)n_ext, S.queue);
-  } else {
-    hipLaunchKernelGGL(k_bin_hist, dim3(grid), dim3(256), 0, stream, A, (uint32_t)n_ext, S.hist);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(256), 0, stream, S.hist);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(256), 0, stream, A, (uint32_t)n_ext,
-                       S.hist, S.queue);
-  }
-  if (ev) (void)hipEventRecord(ev[0], stream);
+  BinRule R = {tu.x_tier1, tu.x_tier2, tu.order == 1 ? 1 : 0};
+  hipLaunchKernelGGL(k_bin_hist, dim3(grid), dim3(256), 0, stream, A, R, (uint32_t)n_ext,
+                     S.hist);
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(256), 0, stream, S.hist, S.ctr + kSeg,
+                     (uint32_t)n_ext);
+  hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(256), 0, stream, A, R, (uint32_t)n_ext,
+                     S.hist, S.queue);
   uint32_t blocks = (uint32_t)device_cus() * (uint32_t)tu.waves_per_cu / 4u;
   if (blocks < 1) blocks = 1;
   if (tu.group_steps == 4)
-    launch_queue_tier<UNIT, 4>(A, S, (uint32_t)n_ext, blocks, stream);
+    launch_tier0<UNIT, 4>(S, blocks, stream);
   else if (tu.group_steps == 16)
-    launch_queue_tier<UNIT, 16>(A, S, (uint32_t)n_ext, blocks, stream);
+    launch_tier0<UNIT, 16>(S, blocks, stream);
   else
-    launch_queue_tier<UNIT, 8>(A, S, (uint32_t)n_ext, blocks, stream);
+    launch_tier0<UNIT, 8>(S, blocks, stream);
   if (ev) (void)hipEventRecord(ev[1], stream);
-  launch_wide<UNIT>(A, S, stream);
+  launch_wide<UNIT>(S, blocks, stream);
   if (ev) (void)hipEventRecord(ev[2], stream);
 }
 
@@ -410,8 +475,10 @@ int check_scoring(int32_t k, int32_t match, int32_t mismatch, int32_t gap) {
 
 int check_tuning(const xd_tuning* t, Tuned& out) {
   out.waves_per_cu = 32;
-  out.group_steps = 8;
+  out.group_steps = 16;
   out.order = 1;
+  out.x_tier1 = 32;
+  out.x_tier2 = 80;
   if (!t) return XD_OK;
   if (t->waves_per_cu) {
     if (t->waves_per_cu < 4 || t->waves_per_cu > 32 || t->waves_per_cu % 4)
@@ -427,6 +494,10 @@ int check_tuning(const xd_tuning* t, Tuned& out) {
     if (t->order != 1 && t->order != 2) return fail(XD_EINVAL, "order must be 1 or 2");
     out.order = t->order;
   }
+  if (t->x_tier1) out.x_tier1 = t->x_tier1;
+  if (t->x_tier2) out.x_tier2 = t->x_tier2;
+  if (out.x_tier1 < 0 || out.x_tier2 < out.x_tier1)
+    return fail(XD_EINVAL, "need 0 <= x_tier1 <= x_tier2");
   return XD_OK;
 }
 
@@ -506,11 +577,14 @@ int enqueue(BatchArgs A, const Scratch& S, bool persistent, const Tuned& tu,
   ProfRecord rec = {};
   if (prof) {
     for (int q = 0; q < 4; ++q) HIP_TRY(hipEventCreate(&rec.ev[q]));
-    HIP_TRY(hipHostMalloc((void**)&rec.counters, 16 * sizeof(uint32_t), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&rec.counters, kCtrWords * sizeof(uint32_t),
+                          hipHostMallocDefault));
     rec.n_ext = n_ext;
   }
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, stream, S.ctr, S.hist);
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, stream, S.ctr, S.hist,
+                     make_pack(A, S, persistent), (uint32_t*)S.targs);
   if (persistent) {
+    if (prof) HIP_TRY(hipEventRecord(rec.ev[0], stream));
     if (A.sc.M == 1)
       launch_persistent_ext<true>(A, S, n_ext, tu, prof ? rec.ev : nullptr, stream);
     else
@@ -525,8 +599,8 @@ int enqueue(BatchArgs A, const Scratch& S, bool persistent, const Tuned& tu,
   hipLaunchKernelGGL(k_combine, dim3((uint32_t)((A.n + 255) / 256)), dim3(256), 0, stream, A);
   if (prof) {
     HIP_TRY(hipEventRecord(rec.ev[3], stream));
-    HIP_TRY(hipMemcpyAsync(rec.counters, S.ctr, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                           stream));
+    HIP_TRY(hipMemcpyAsync(rec.counters, S.ctr, kCtrWords * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, stream));
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_pending.push_back(rec);
   }
@@ -771,8 +845,9 @@ int xd_profile_read(xd_profile* out, int reset) {
     HIP_TRY(hipEventElapsedTime(&tt, r.ev[0], r.ev[3]));
     g_prof_sum.batches += 1;
     g_prof_sum.extensions += r.n_ext;
-    g_prof_sum.to_tier2 += r.counters[0];
-    g_prof_sum.to_tier3 += r.counters[2];
+    g_prof_sum.to_tier2 += r.counters[kOvfCount + 0];
+    g_prof_sum.to_tier3 += r.counters[kOvfCount + 1];
+    g_prof_sum.to_tier4 += r.counters[kOvfCount + 2];
     g_prof_sum.ms_tier1 += t1;
     g_prof_sum.ms_wide += t2;
     g_prof_sum.ms_combine += t3;

@@ -77,6 +77,19 @@ struct Tier {
   static constexpr int LDS_WORDS = RING + MIR;
 };
 
+// calls f(std::integral_constant<int, 0>) ... f(std::integral_constant<int, N-1>)
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for_impl(F& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for_impl<I + 1, N>(f);
+  }
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F& f) {
+  static_for_impl<0, N>(f);
+}
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 
 __device__ __forceinline__ uint32_t code_at(const uint32_t* __restrict__ w, int32_t p) {
@@ -121,6 +134,30 @@ __device__ __forceinline__ int32_t add_nonzero(int32_t acc, int32_t add, uint64_
   return r;
 }
 
+// One improvement step for match == 1, on the scalar unit:
+//   if (imp != 0) { last = imp; lastt = TT; }   thr += g + (imp != 0)
+// (the selects read the SCC of the compare; s_addc then consumes it).  TT is
+// the step's position in its group, an immediate.
+template <int TT>
+__device__ __forceinline__ void unit_improve(uint64_t imp, int32_t g, int32_t& thr,
+                                             uint64_t& last, int32_t& lastt) {
+  const int32_t a = __builtin_amdgcn_readfirstlane(thr);
+  const int32_t b = __builtin_amdgcn_readfirstlane(g);
+  int32_t r, lt = __builtin_amdgcn_readfirstlane(lastt);
+  uint64_t l = last;
+  asm volatile(
+      "s_cmp_lg_u64 %3, 0\n\t"
+      "s_cselect_b64 %1, %3, %1\n\t"
+      "s_cselect_b32 %2, %4, %2\n\t"
+      "s_addc_u32 %0, %5, %6"
+      : "=s"(r), "+s"(l), "+s"(lt)
+      : "s"(imp), "i"(TT), "s"(a), "s"(b)
+      : "scc");
+  thr = r;
+  last = l;
+  lastt = lt;
+}
+
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
@@ -134,10 +171,11 @@ __device__ __forceinline__ void wave_lds_fence() {
 // UNIT: match == 1.  Then a cell of antidiagonal d scores at most T_{d-1} + 1,
 // so an improving cell is exactly T_{d-1} + 1 and no max-reduction is needed.
 template <int CPL, int GS, bool UNIT>
-__device__ bool extend(const Ext& e, const Scoring& sc, uint32_t* __restrict__ ring,
-                       ExtOut& res) {
+__device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
+                                       uint32_t* __restrict__ ring, ExtOut& res) {
   using TI = Tier<CPL, GS>;
   constexpr int Q = TI::Q;
+  constexpr int kShort = GS < 4 ? GS : 4;  // group length near the window's top
   constexpr int RING = TI::RING;
   constexpr int MASK = RING - 1;
   constexpr int MIR = TI::MIR;
@@ -197,26 +235,32 @@ __device__ bool extend(const Ext& e, const Scoring& sc, uint32_t* __restrict__ r
   uint64_t cnt = 0;  // evaluated cells (wave-uniform)
   int32_t irow = lane * CPL;  // row of this lane's slot 0 minus base
 
-  // GS antidiagonals d+1 .. d+GS
-  auto group = [&](auto masked_tag) {
+  // G antidiagonals d+1 .. d+G (G = GS, or 4 when the band is near the top
+  // of the window)
+  auto group = [&](auto masked_tag, auto len_tag) {
     constexpr bool MASKED = decltype(masked_tag)::value;
+    constexpr int G = decltype(len_tag)::value;
     // ring index of slot CPL-1 of this lane at antidiagonal d+1
     const int32_t r = (d + 1 - base - irow - (CPL - 1)) & MASK;
-    uint32_t bmv[GS][CPL];
+    uint32_t bmv[G][CPL];
 #pragma unroll
-    for (int t = 0; t < GS; ++t)
+    for (int t = 0; t < G; ++t)
 #pragma unroll
       for (int c = 0; c < CPL; ++c) bmv[t][c] = ring[r + t + (CPL - 1 - c)];
-    uint64_t impM[GS][CPL];
-    uint32_t gcnt = 0;  // evaluated cells in this group (<= GS * 64 * CPL)
+    uint64_t last[CPL];  // improving cells of the last improving antidiagonal
 #pragma unroll
-    for (int t = 0; t < GS; ++t) {
+    for (int c = 0; c < CPL; ++c) last[c] = 0;
+    int32_t lastt = 0;   // its position in the group (1-based), 0 = none
+    uint32_t gcnt = 0;   // evaluated cells in this group (<= G * 64 * CPL)
+    auto body = [&](auto t_tag) {
+      constexpr int t = decltype(t_tag)::value;
       const int32_t dn = d + 1 + t;
       const int32_t timp = thr + X;
       int32_t upv[CPL];
       upv[0] = shr1_zero(U1[CPL - 1]);
 #pragma unroll
       for (int c = 1; c < CPL; ++c) upv[c] = U1[c - 1];
+      uint64_t imp[CPL];
       uint64_t any = 0;
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
@@ -229,53 +273,53 @@ __device__ bool extend(const Ext& e, const Scoring& sc, uint32_t* __restrict__ r
         }
         const bool lv = s >= thr;
         gcnt += (uint32_t)__builtin_popcountll(ballot64(s > kEvMin));
-        impM[t][c] = ballot64(s > timp);
-        any |= impM[t][c];
-        if (t >= GS - 2) {
+        imp[c] = ballot64(s > timp);
+        any |= imp[c];
+        if (t >= G - 2) {
           Lp[c] = Lc[c];
           Lc[c] = ballot64(lv);
         }
         Up[c] = upv[c];
         U1[c] = lv ? s : 0;
       }
-      if (UNIT) {
-        thr = add_nonzero(thr, g, any);  // T rises by exactly 1 on improvement
-        continue;
-      }
-      int32_t dT = 0;
-      if (any) {
-        int32_t v = 0;
+      if constexpr (UNIT && CPL == 1) {
+        // T rises by exactly 1 on improvement
+        unit_improve<t + 1>(any, g, thr, last[0], lastt);
+      } else {
+        int32_t dT = 0;
+        if (any) {
+          if (UNIT) {
+            dT = 1;
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) v = max(v, U1[c]);
-        const int32_t vmax = __builtin_amdgcn_readfirstlane(wave_max_i32(v));
-        dT = vmax - timp;
-        // the arg-max candidates are the cells holding the new best
+            for (int c = 0; c < CPL; ++c) last[c] = imp[c];
+          } else {
+            int32_t v = 0;
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) impM[t][c] = ballot64(U1[c] == vmax);
-      }
-      thr += g + dT;
-    }
-    cnt += gcnt;
-    // arg-max: the last antidiagonal of the group that improved, its
-    // improving cell with the smallest row
+            for (int c = 0; c < CPL; ++c) v = max(v, U1[c]);
+            const int32_t vmax = __builtin_amdgcn_readfirstlane(wave_max_i32(v));
+            dT = vmax - timp;
+            // the arg-max candidates are the cells holding the new best
 #pragma unroll
-    for (int t = GS - 1; t >= 0; --t) {
-      uint64_t any = 0;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) any |= impM[t][c];
-      if (any) {
-        int32_t cell = 0x7fffffff;
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-          const uint64_t at = impM[t][c];
-          if (at) cell = min(cell, (int32_t)__builtin_ctzll(at) * CPL + c);
+            for (int c = 0; c < CPL; ++c) last[c] = ballot64(U1[c] == vmax);
+          }
+          lastt = t + 1;
         }
-        bi = base + cell;
-        dstar = d + 1 + t;
-        break;
+        thr += g + dT;
       }
+    };
+    static_for<G>(body);
+    cnt += gcnt;
+    // arg-max: the improving cell with the smallest row on the last
+    // antidiagonal of the group that improved
+    if (lastt) {
+      int32_t cell = 0x7fffffff;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c)
+        if (last[c]) cell = min(cell, (int32_t)__builtin_ctzll(last[c]) * CPL + c);
+      bi = base + cell;
+      dstar = d + lastt;
     }
-    d += GS;
+    d += G;
   };
 
   bool overflow = false;
@@ -292,32 +336,44 @@ __device__ bool extend(const Ext& e, const Scoring& sc, uint32_t* __restrict__ r
     if (hi < 0 || d >= m + n) break;  // two dead antidiagonals, or grid done
     if (hi + GS > Q - 1) {
       const int32_t sl = lo / CPL;  // whole lanes below the band
-      if (sl == 0 || hi - sl * CPL + GS > Q - 1) {
+      if (hi - sl * CPL + kShort > Q - 1) {  // cannot fit even a short group
         overflow = true;
         break;
       }
-      const int src = lane + sl;
-      const bool inside = src < 64;
+      if (sl > 0) {
+        const int src = lane + sl;
+        const bool inside = src < 64;
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int32_t u1 = __builtin_amdgcn_ds_bpermute((src & 63) << 2, U1[c]);
-        const int32_t up = __builtin_amdgcn_ds_bpermute((src & 63) << 2, Up[c]);
-        U1[c] = inside ? u1 : 0;
-        Up[c] = inside ? up : 0;
-        Lc[c] >>= sl;
-        Lp[c] >>= sl;
+        for (int c = 0; c < CPL; ++c) {
+          const int32_t u1 = __builtin_amdgcn_ds_bpermute((src & 63) << 2, U1[c]);
+          const int32_t up = __builtin_amdgcn_ds_bpermute((src & 63) << 2, Up[c]);
+          U1[c] = inside ? u1 : 0;
+          Up[c] = inside ? up : 0;
+          Lc[c] >>= sl;
+          Lp[c] >>= sl;
+        }
+        base += sl * CPL;
+        hi -= sl * CPL;
+        lo -= sl * CPL;
+        load_a();
       }
-      base += sl * CPL;
-      hi -= sl * CPL;
-      lo -= sl * CPL;
-      load_a();
     }
+    // a full group when the band can grow GS rows inside the window, else a
+    // short one
+    const bool full = hi + GS <= Q - 1;
     fill_to(d + GS - base);
-    const bool fast = (base + hi + GS <= m) && (base + lo >= d + GS - n);
-    if (fast) {
-      group(std::false_type{});
+    if (full) {
+      const bool fast = (base + hi + GS <= m) && (base + lo >= d + GS - n);
+      if (fast)
+        group(std::false_type{}, std::integral_constant<int, GS>{});
+      else
+        group(std::true_type{}, std::integral_constant<int, GS>{});
     } else {
-      group(std::true_type{});
+      const bool fast = (base + hi + kShort <= m) && (base + lo >= d + kShort - n);
+      if (fast)
+        group(std::false_type{}, std::integral_constant<int, kShort>{});
+      else
+        group(std::true_type{}, std::integral_constant<int, kShort>{});
     }
   }
   if (overflow) return false;

@@ -185,7 +185,8 @@ def test_store_info():
 
 
 TUNINGS = [dict(), dict(waves_per_cu=8, group_steps=4), dict(waves_per_cu=16, group_steps=16),
-           dict(order=2, group_steps=8)]
+           dict(order=2, group_steps=8), dict(x_tier1=5, x_tier2=30),
+           dict(x_tier1=1000, x_tier2=1000)]
 
 
 @pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: str(sorted(t.items())))
