@@ -156,6 +156,75 @@ int xd_plan_create(const xd_store* store, const uint32_t* pairs, const uint32_t*
 int xd_plan_launch(xd_plan* plan, void* hip_stream);
 void xd_plan_destroy(xd_plan* plan);
 
+/* ---- serving ------------------------------------------------------------ */
+
+/* A request server over a resident read store.  Requests (host task arrays,
+ * copied at submission) wait in FIFO order and are admitted when one of
+ * `slots` batch slots is free and their device bytes (xd_server_request_bytes)
+ * fit in what hbm_budget_bytes has left.  Every waiting request that fits is
+ * packed into the next batch (up to max_batch_tasks tasks), which runs the
+ * batched form on the slot's own stream; batches in different slots overlap
+ * on the device, and requests arriving meanwhile are admitted as slots and
+ * memory free up.  A request's results are identical to aligning it alone.
+ * All device work happens on one internal thread; the calls below are
+ * thread-safe.  Times are seconds since the server was created. */
+typedef struct xd_server xd_server;
+
+typedef struct {
+  uint64_t hbm_budget_bytes; /* device bytes for requests in flight (0 = 1 GiB) */
+  int32_t slots;             /* batches in flight at once, 1..64 (0 = 4) */
+  int32_t max_batch_tasks;   /* tasks per batch (0 = 262144) */
+  int32_t max_pending;       /* queued requests before submit says XD_EAGAIN (0 = 65536) */
+  int32_t k, match, mismatch, gap; /* as for xd_align_batch */
+  xd_tuning tuning;          /* for the batched form; zeros = defaults */
+} xd_server_config;
+
+typedef struct {
+  double t_submit, t_start, t_done; /* submission, batch launch, results on the host */
+  uint64_t batch;                   /* batch that carried the request */
+  uint64_t batch_tasks;             /* tasks in that batch */
+} xd_request_info;
+
+typedef struct {
+  uint64_t submitted, completed, cancelled, batches, tasks, cells;
+  uint64_t peak_inflight_bytes;     /* highest admitted device bytes */
+  int32_t peak_busy_slots;          /* most batches in flight at once */
+  int32_t reserved;
+  double busy_s;                    /* summed device time of the batches */
+  uint64_t pending;                 /* requests waiting now */
+  uint64_t inflight_bytes;          /* admitted device bytes now */
+} xd_server_counters;
+
+/* Device bytes a request of n tasks holds while in flight. */
+uint64_t xd_server_request_bytes(uint64_t n);
+
+/* The store must outlive the server.  Scoring checks as xd_align_batch. */
+int xd_server_create(const xd_store* store, const xd_server_config* cfg, xd_server** out);
+
+/* Copies the request (host pointers; x may be NULL to use x_scalar).
+ * XD_EINVAL: bad arguments or a request larger than the whole budget;
+ * XD_EAGAIN: max_pending requests already waiting. */
+int xd_server_submit(xd_server* server, const uint32_t* pairs, const uint32_t* seeds,
+                     const int32_t* x, int32_t x_scalar, uint64_t n, uint64_t* req_id);
+
+/* Waits up to timeout_ms (0 = do not wait, < 0 = no limit) for the request.
+ * XD_OK: results copied to the host arrays (any may be NULL; sizes as for
+ * xd_align_batch) and the request released; XD_EAGAIN: not finished yet;
+ * XD_EINVAL: unknown id; XD_EDEVICE / XD_ENOMEM: its batch failed. */
+int xd_server_poll(xd_server* server, uint64_t req_id, int32_t timeout_ms, int32_t* score,
+                   uint32_t* beg, uint32_t* end, int32_t* status, uint64_t* cells,
+                   xd_request_info* info);
+
+/* Drops a request: removed if still waiting, discarded when its batch ends
+ * if already running. */
+int xd_server_cancel(xd_server* server, uint64_t req_id);
+
+/* Counters; returns the code of the last batch failure, if any. */
+int xd_server_stats(xd_server* server, xd_server_counters* out);
+
+/* Waits for running batches, then frees everything. */
+void xd_server_destroy(xd_server* server);
+
 /* ---- profiling ----------------------------------------------------------- */
 
 /* Per-kernel timing of the batch pipeline, for benchmarks and roofline

@@ -213,3 +213,84 @@ def profile_read(reset: bool = True) -> dict:
     p = _lib.Profile()
     _lib.check(_lib.load().xd_profile_read(ctypes.byref(p), 1 if reset else 0))
     return {f: getattr(p, f) for f, _ in _lib.Profile._fields_}
+
+
+def request_bytes(n: int) -> int:
+    """Device bytes a server request of n tasks holds while in flight."""
+    return int(_lib.load().xd_server_request_bytes(int(n)))
+
+
+class Server:
+    """Request server over a resident read store (xd_server).
+
+    submit() copies host task arrays and returns a request id; poll() returns
+    None while the request is pending, else its results (host numpy arrays)
+    and timing info.
+    """
+
+    def __init__(self, store, hbm_budget_bytes=0, slots=0, max_batch_tasks=0, max_pending=0,
+                 k=17, match=1, mismatch=-1, gap=-1, tuning=None):
+        t = tuning or {}
+        cfg = _lib.ServerConfig(int(hbm_budget_bytes), int(slots), int(max_batch_tasks),
+                                int(max_pending), int(k), int(match), int(mismatch), int(gap),
+                                _lib.Tuning(int(t.get("waves_per_cu", 0)),
+                                            int(t.get("group_steps", 0)), int(t.get("order", 0)),
+                                            int(t.get("x_tier1", 0)), int(t.get("x_tier2", 0))))
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().xd_server_create(store.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._store = store
+        self._n = {}
+
+    def submit(self, pairs, seeds, x=None, x_scalar=0) -> int:
+        pairs = np.ascontiguousarray(pairs, np.uint32).reshape(-1, 2)
+        seeds = np.ascontiguousarray(seeds, np.uint32).reshape(-1, 2)
+        n = pairs.shape[0]
+        xs = None if x is None else np.ascontiguousarray(x, np.int32)
+        rid = ctypes.c_uint64()
+        _lib.check(_lib.load().xd_server_submit(self._h, _p(pairs), _p(seeds), _p(xs),
+                                                int(x_scalar), n, ctypes.byref(rid)))
+        self._n[rid.value] = n
+        return rid.value
+
+    def poll(self, rid: int, timeout_ms: int = 0):
+        n = self._n[rid]
+        out = dict(score=np.empty(n, np.int32), beg=np.empty((n, 2), np.uint32),
+                   end=np.empty((n, 2), np.uint32), status=np.empty(n, np.int32),
+                   cells=np.empty(n, np.uint64))
+        info = _lib.RequestInfo()
+        rc = _lib.load().xd_server_poll(self._h, rid, int(timeout_ms), _p(out["score"]),
+                                        _p(out["beg"]), _p(out["end"]), _p(out["status"]),
+                                        _p(out["cells"]), ctypes.byref(info))
+        if rc == _lib.XD_EAGAIN:
+            return None
+        del self._n[rid]
+        _lib.check(rc)
+        out["info"] = {f: getattr(info, f) for f, _ in _lib.RequestInfo._fields_}
+        return out
+
+    def cancel(self, rid: int) -> None:
+        _lib.check(_lib.load().xd_server_cancel(self._h, rid))
+        self._n.pop(rid, None)
+
+    def stats(self) -> dict:
+        c = _lib.ServerCounters()
+        _lib.check(_lib.load().xd_server_stats(self._h, ctypes.byref(c)))
+        return {f: getattr(c, f) for f, _ in _lib.ServerCounters._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.load().xd_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -18,7 +18,8 @@ EXPORTS = (
     "xd_pack_reads", "xd_store_create", "xd_store_create_from_codes", "xd_store_destroy",
     "xd_store_info", "xd_align_batch", "xd_align_batch_persistent", "xd_plan_create",
     "xd_plan_launch", "xd_plan_destroy", "xd_profile_enable", "xd_profile_read",
-    "xd_last_error",
+    "xd_server_request_bytes", "xd_server_create", "xd_server_submit", "xd_server_poll",
+    "xd_server_cancel", "xd_server_stats", "xd_server_destroy", "xd_last_error",
 )
 
 
@@ -26,6 +27,28 @@ class Tuning(ctypes.Structure):
     _fields_ = [("waves_per_cu", ctypes.c_int32), ("group_steps", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("x_tier1", ctypes.c_int32),
                 ("x_tier2", ctypes.c_int32)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("slots", ctypes.c_int32),
+                ("max_batch_tasks", ctypes.c_int32), ("max_pending", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("match", ctypes.c_int32), ("mismatch", ctypes.c_int32),
+                ("gap", ctypes.c_int32), ("tuning", Tuning)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("batch", ctypes.c_uint64),
+                ("batch_tasks", ctypes.c_uint64)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("cancelled", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("tasks", ctypes.c_uint64), ("cells", ctypes.c_uint64),
+                ("peak_inflight_bytes", ctypes.c_uint64), ("peak_busy_slots", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("busy_s", ctypes.c_double),
+                ("pending", ctypes.c_uint64), ("inflight_bytes", ctypes.c_uint64)]
 
 
 class Profile(ctypes.Structure):
@@ -78,6 +101,20 @@ def load() -> ctypes.CDLL:
     lib.xd_plan_launch.restype = ctypes.c_int
     lib.xd_plan_destroy.argtypes = [vp]
     lib.xd_plan_destroy.restype = None
+    lib.xd_server_request_bytes.argtypes = [u64]
+    lib.xd_server_request_bytes.restype = u64
+    lib.xd_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    lib.xd_server_create.restype = ctypes.c_int
+    lib.xd_server_submit.argtypes = [vp, vp, vp, vp, i32, u64, ctypes.POINTER(u64)]
+    lib.xd_server_submit.restype = ctypes.c_int
+    lib.xd_server_poll.argtypes = [vp, u64, i32, vp, vp, vp, vp, vp, ctypes.POINTER(RequestInfo)]
+    lib.xd_server_poll.restype = ctypes.c_int
+    lib.xd_server_cancel.argtypes = [vp, u64]
+    lib.xd_server_cancel.restype = ctypes.c_int
+    lib.xd_server_stats.argtypes = [vp, ctypes.POINTER(ServerCounters)]
+    lib.xd_server_stats.restype = ctypes.c_int
+    lib.xd_server_destroy.argtypes = [vp]
+    lib.xd_server_destroy.restype = None
     lib.xd_profile_enable.argtypes = [ctypes.c_int]
     lib.xd_profile_enable.restype = ctypes.c_int
     lib.xd_profile_read.argtypes = [ctypes.POINTER(Profile), ctypes.c_int]

@@ -621,6 +621,12 @@ int batch_async(const BatchArgs& A, bool persistent, const Tuned& tu, hipStream_
 
 }  // namespace
 
+// for the other translation units of the library (not exported)
+__attribute__((visibility("hidden"))) int xd_internal_fail(int code, const char* msg) {
+  g_err = msg ? msg : "";
+  return code;
+}
+
 extern "C" {
 
 const char* xd_last_error(void) { return g_err.c_str(); }

@@ -51,6 +51,9 @@ CONFIGS = {
     "c3-small": dict(seed=13, genome_len=150_000, mode=1, depth=30.0, len_dist=1,
                      len_mean=10_000.0, len_sd=5_000.0, len_min=1_000, len_max=50_000,
                      n_tasks=3_000, seeds_per_pair=1, x=(7, 25, 50)),
+    "c5-small": dict(seed=15, genome_len=300_000, mode=1, depth=30.0, len_dist=1,
+                     len_mean=10_000.0, len_sd=5_000.0, len_min=1_000, len_max=100_000,
+                     n_tasks=6_000, seeds_per_pair=1, x=(7, 25)),
     "c4-small": dict(seed=14, genome_len=900_000, n_rep_src=4, rep_len=5_000, n_rep_copies=20,
                      mode=1, depth=30.0, len_dist=1, len_mean=12_000.0, len_sd=6_000.0,
                      len_min=1_000, len_max=60_000, p_sub=0.04, p_ins=0.04, p_del=0.04,
