@@ -27,8 +27,11 @@
 //
 // b is read through a per-wave LDS ring of encoded bases:
 //   ring[j mod RING] = (match - mismatch) << (8 * code(b_j))
-// and a lane's own a_i is kept as 8*code(a_i), so one v_bfe_u32 gives the
-// match bonus of a cell.
+// read one byte at a time at byte offset code(a_i) within the word, so one
+// ds_read_u8 gives a cell's match bonus.  The codes of a sit in a second
+// ring (one byte per row).  Both rings are refilled 64 positions at a time
+// from the packed read store; the next chunk is always already on its way
+// in a register (loaded one refill ahead), so refills do not wait for HBM.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -68,13 +71,19 @@ struct Ext {
 template <int CPL, int GS>
 struct Tier {
   static constexpr int Q = 64 * CPL;         // window rows
+  // b ring (one word per j): holds every j the window can need between
+  // refills, including after a re-centring jump of up to Q rows
   static constexpr int kNeed = 2 * Q + 64 + GS + 2;
   static constexpr int RING = kNeed <= 256 ? 256
                               : kNeed <= 512 ? 512
                               : kNeed <= 1024 ? 1024
                               : kNeed <= 2048 ? 2048 : 4096;
-  static constexpr int MIR = CPL + GS;       // mirrored slots after the ring
-  static constexpr int LDS_WORDS = RING + MIR;
+  static constexpr int MIR = CPL + GS;       // mirrored words after the ring
+  // a ring (one byte per i): the window's rows plus one refill chunk
+  static constexpr int RA = Q + 64 <= 128 ? 128
+                            : Q + 64 <= 256 ? 256
+                            : Q + 64 <= 512 ? 512 : 2048;
+  static constexpr int LDS_WORDS = RING + MIR + RA / 4;
 };
 
 // calls f(std::integral_constant<int, 0>) ... f(std::integral_constant<int, N-1>)
@@ -191,34 +200,59 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
   int32_t base = 0;
   int32_t U1[CPL];  // U on the last computed antidiagonal (0 = dead)
   int32_t Up[CPL];  // U on the one before, shifted up by one cell
-  uint32_t aa[CPL];
+  uint32_t aa[CPL]; // code of a_i for the lane's cells (byte offset in a b word)
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
     U1[c] = (lane == 0 && c == 0) ? bias : 0;  // the origin, U(0,0) = bias
     Up[c] = 0;
   }
-  auto load_a = [&]() {
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      const int32_t i = base + lane * CPL + c;
-      aa[c] = (i >= 1 & i <= m) ? 8u * code_at(e.wa, e.oa + e.dir * (i - 1)) : 0u;
-    }
-  };
-  load_a();
+  constexpr int RA = TI::RA;
+  uint8_t* aring = (uint8_t*)(ring + RING + MIR);
 
+  // packed word holding position p of a read, or 0 outside [lo, hi]
+  auto word_of = [&](const uint32_t* w, int32_t o, int32_t q, int32_t lim) -> uint32_t {
+    uint32_t v = 0;
+    if (q >= 1 & q <= lim) v = w[(o + e.dir * (q - 1)) >> 4];
+    return v;
+  };
+  auto code_in = [&](uint32_t w, int32_t o, int32_t q) -> uint32_t {
+    return (w >> (((o + e.dir * (q - 1)) & 15) << 1)) & 3u;
+  };
+
+  // b ring: chunk c holds j in [64c, 64c+63]; pf_b carries the next chunk
   int32_t filled = -1;  // highest j whose ring slot holds b_j
+  uint32_t pf_b = word_of(e.wb, e.ob, lane, n);
   auto fill_to = [&](int32_t jhi) {
     while (filled < jhi) {
       const int32_t j = filled + 1 + lane;
-      const uint32_t v =
-          (j >= 1 & j <= n) ? (dM << (8u * code_at(e.wb, e.ob + e.dir * (j - 1)))) : 0u;
+      const uint32_t v = (j >= 1 & j <= n) ? (dM << (8u * code_in(pf_b, e.ob, j))) : 0u;
       const int slot = j & MASK;
       ring[slot] = v;
       if (slot < MIR) ring[RING + slot] = v;
+      pf_b = word_of(e.wb, e.ob, j + 64, n);  // the chunk after, on its way
       filled += 64;
     }
     wave_lds_fence();
   };
+
+  // a ring: chunk c holds i in [64c, 64c+63] (code 0 outside 1..m)
+  int32_t filled_a = -1;
+  uint32_t pf_a = word_of(e.wa, e.oa, lane, m);
+  auto fill_a_to = [&](int32_t ihi) {
+    while (filled_a < ihi) {
+      const int32_t i = filled_a + 1 + lane;
+      aring[i & (RA - 1)] = (uint8_t)((i >= 1 & i <= m) ? code_in(pf_a, e.oa, i) : 0u);
+      pf_a = word_of(e.wa, e.oa, i + 64, m);
+      filled_a += 64;
+    }
+    wave_lds_fence();
+  };
+  auto load_a = [&]() {
+    fill_a_to(base + Q - 1);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) aa[c] = aring[(base + lane * CPL + c) & (RA - 1)];
+  };
+  load_a();
 
   // live masks per slot: Lc for the last antidiagonal d, Lp for d-1
   uint64_t Lc[CPL], Lp[CPL];
@@ -232,7 +266,7 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
   // threshold for antidiagonal d+1 in U units: T_d - X + g*(d+1) + bias;
   // the improvement threshold is thr + X
   int32_t thr = g + kBias0;
-  uint64_t cnt = 0;  // evaluated cells (wave-uniform)
+  uint32_t cnt = 0;  // evaluated cells of this lane
   int32_t irow = lane * CPL;  // row of this lane's slot 0 minus base
 
   // G antidiagonals d+1 .. d+G (G = GS, or 4 when the band is near the top
@@ -242,16 +276,20 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
     constexpr int G = decltype(len_tag)::value;
     // ring index of slot CPL-1 of this lane at antidiagonal d+1
     const int32_t r = (d + 1 - base - irow - (CPL - 1)) & MASK;
+    // byte address of this lane's match bonus for slot c at the group's
+    // first antidiagonal; step t adds 4*t
+    const uint8_t* rbytes = (const uint8_t*)ring;
     uint32_t bmv[G][CPL];
 #pragma unroll
-    for (int t = 0; t < G; ++t)
+    for (int c = 0; c < CPL; ++c) {
+      const uint32_t ad = ((uint32_t)(r + (CPL - 1 - c)) << 2) + aa[c];
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) bmv[t][c] = ring[r + t + (CPL - 1 - c)];
+      for (int t = 0; t < G; ++t) bmv[t][c] = rbytes[ad + 4 * t];
+    }
     uint64_t last[CPL];  // improving cells of the last improving antidiagonal
 #pragma unroll
     for (int c = 0; c < CPL; ++c) last[c] = 0;
     int32_t lastt = 0;   // its position in the group (1-based), 0 = none
-    uint32_t gcnt = 0;   // evaluated cells in this group (<= G * 64 * CPL)
     auto body = [&](auto t_tag) {
       constexpr int t = decltype(t_tag)::value;
       const int32_t dn = d + 1 + t;
@@ -264,15 +302,14 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
       uint64_t any = 0;
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
-        const int32_t tv = (int32_t)__builtin_amdgcn_ubfe(bmv[t][c], aa[c], 8);
-        int32_t s = max(max(Up[c] + tv + C, upv[c]), U1[c]);
+        int32_t s = max(max(Up[c] + (int32_t)bmv[t][c] + C, upv[c]), U1[c]);
         if (MASKED) {
           const int32_t i = base + irow + c;
           const bool out = (i > m) | (i < dn - n);
           s = out ? 0 : s;
         }
         const bool lv = s >= thr;
-        gcnt += (uint32_t)__builtin_popcountll(ballot64(s > kEvMin));
+        cnt += (s > kEvMin) ? 1u : 0u;
         imp[c] = ballot64(s > timp);
         any |= imp[c];
         if (t >= G - 2) {
@@ -308,7 +345,6 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
       }
     };
     static_for<G>(body);
-    cnt += gcnt;
     // arg-max: the improving cell with the smallest row on the last
     // antidiagonal of the group that improved
     if (lastt) {
@@ -333,7 +369,8 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
         hi = max(hi, (63 - (int32_t)__builtin_clzll(mm)) * CPL + c);
       }
     }
-    if (hi < 0 || d >= m + n) break;  // two dead antidiagonals, or grid done
+    // two dead antidiagonals (hi < 0), or the grid is done (d >= m+n)
+    if ((hi | (m + n - 1 - d)) < 0) break;
     if (hi + GS > Q - 1) {
       const int32_t sl = lo / CPL;  // whole lanes below the band
       if (hi - sl * CPL + kShort > Q - 1) {  // cannot fit even a short group
@@ -362,14 +399,16 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
     // short one
     const bool full = hi + GS <= Q - 1;
     fill_to(d + GS - base);
+    // fast: the band stays clear of both walls (i <= m, j <= n) for the group
+    const int32_t room_a = m - base - hi, room_b = base + lo - d + n;
     if (full) {
-      const bool fast = (base + hi + GS <= m) && (base + lo >= d + GS - n);
+      const bool fast = ((room_a - GS) | (room_b - GS)) >= 0;
       if (fast)
         group(std::false_type{}, std::integral_constant<int, GS>{});
       else
         group(std::true_type{}, std::integral_constant<int, GS>{});
     } else {
-      const bool fast = (base + hi + kShort <= m) && (base + lo >= d + kShort - n);
+      const bool fast = ((room_a - kShort) | (room_b - kShort)) >= 0;
       if (fast)
         group(std::false_type{}, std::integral_constant<int, kShort>{});
       else
@@ -377,7 +416,7 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
     }
   }
   if (overflow) return false;
-  const uint64_t cells = cnt;
+  const uint64_t cells = wave_sum_u64(cnt);
   // thr = T - X + g*(d+1) + bias after the last antidiagonal d
   res.best = thr + X - g * (d + 1) - bias;
   res.bi = bi;
