@@ -211,7 +211,7 @@ def main():
                 "cells_per_launch": cells_per_step, "ops_per_cell": OPS_PER_CELL,
                 "kernel_gcups": round(cells_per_step / (k_ms / 1e3) / 1e9, 2),
                 "ext_overflowed": [int(prof["to_tier2"]), int(prof["to_tier3"]),
-                                   int(prof["to_tier4"])]}
+                                   int(prof["to_tier4"]), int(prof["to_band"])]}
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.int32, device=dev)  # 1 GiB

@@ -59,8 +59,8 @@ extern "C" {
 #define XD_TASK_BAD_READ 1 /* a read id >= n_reads */
 #define XD_TASK_BAD_SEED 2 /* pa + k > len(A) or pb + k > len(B) */
 #define XD_TASK_BAD_X 3    /* X < 0 or X > XD_X_MAX */
-#define XD_TASK_BAND_OVERFLOW 4 /* the live band outgrew the widest register window
-                                   (1024 cells); no result is produced */
+#define XD_TASK_BAND_OVERFLOW 4 /* reserved: no longer produced (bands wider than the
+                                   1024-cell window run in the band tier) */
 
 /* limits (checked; violations return XD_EINVAL) */
 #define XD_X_MAX (1 << 20)           /* largest X */
@@ -109,7 +109,9 @@ int xd_store_info(const xd_store* store, uint64_t* device_bytes, uint32_t* n_rea
  *   cells  uint64[n]   out, may be NULL; evaluated cells, 0 when status != 0
  * hip_stream: a hipStream_t (NULL = the default stream).  The call is
  * asynchronous: it validates the scalar arguments, enqueues kernels and a
- * stream-ordered scratch allocation, and returns.  k >= 1.  n = 0 is a no-op.
+ * stream-ordered scratch allocation, and returns.  The scratch is about 90
+ * bytes per task plus the band tier's rows (xd_tuning.band_blocks; at most
+ * 64 MiB by default).  k >= 1.  n = 0 is a no-op.
  * Invalid scalars (k, scores, x_scalar when x == NULL) -> XD_EINVAL, nothing
  * enqueued. */
 int xd_align_batch(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,
@@ -128,7 +130,11 @@ typedef struct {
   int32_t x_tier1;      /* tasks with X <= x_tier1 start in the 64-cell window (default 32) */
   int32_t x_tier2;      /* X <= x_tier2 start in the 128-cell window (default 80); larger X
                            start in the 256-cell window.  An extension whose band outgrows its
-                           window is re-run in the next wider one (64, 128, 256, 1024). */
+                           window is re-run in the next wider one (64, 128, 256, 1024), and
+                           past 1024 cells in the band tier (band kept in device memory). */
+  int32_t band_blocks;  /* workgroups of the band tier, 0..1024; each holds 12 * (longest read
+                           of the store + 64) bytes or so of scratch.  0 = as many as fit in
+                           64 MiB, at most 16 */
 } xd_tuning;
 
 /* Same contract and results as xd_align_batch.  Extensions are ordered on
@@ -198,6 +204,12 @@ typedef struct {
 /* Device bytes a request of n tasks holds while in flight. */
 uint64_t xd_server_request_bytes(uint64_t n);
 
+/* Device bytes a server on this store holds whatever its load: each slot's
+ * band-tier rows (cfg->tuning.band_blocks workgroups, 0 = 1).  The requests
+ * in flight share hbm_budget_bytes minus this; xd_server_create fails with
+ * XD_EINVAL when nothing is left.  0 when store or cfg is NULL. */
+uint64_t xd_server_fixed_bytes(const xd_store* store, const xd_server_config* cfg);
+
 /* The store must outlive the server.  Scoring checks as xd_align_batch. */
 int xd_server_create(const xd_store* store, const xd_server_config* cfg, xd_server** out);
 
@@ -238,9 +250,10 @@ typedef struct {
   uint64_t to_tier2;      /* extensions moved from the 64- to the 128-cell window */
   uint64_t to_tier3;      /* moved from the 128- to the 256-cell window */
   uint64_t to_tier4;      /* moved from the 256- to the 1024-cell window */
+  uint64_t to_band;       /* moved from the 1024-cell window to the band tier */
   double ms_tier1;        /* summed time of the 64-cell tier (and, in the batched form,
                              the queue build before it) */
-  double ms_wide;         /* summed time of the 128-, 256- and 1024-cell tiers */
+  double ms_wide;         /* summed time of the 128-, 256- and 1024-cell and band tiers */
   double ms_combine;      /* summed time of the combine kernel */
   double ms_total;        /* first to last event, summed over calls */
 } xd_profile;

@@ -108,9 +108,12 @@ def _tuning(t):
         return None
     if isinstance(t, _lib.Tuning):
         return ctypes.byref(t)
-    s = _lib.Tuning(int(t.get("waves_per_cu", 0)), int(t.get("group_steps", 0)),
-                    int(t.get("order", 0)), int(t.get("x_tier1", 0)), int(t.get("x_tier2", 0)))
-    return ctypes.byref(s)
+    return ctypes.byref(_tuning_struct(t))
+
+
+def _tuning_struct(t) -> "_lib.Tuning":
+    t = t or {}
+    return _lib.Tuning(*(int(t.get(f, 0)) for f, _ in _lib.Tuning._fields_))
 
 
 def _alloc_out(n, dev, with_cells):
@@ -148,8 +151,8 @@ def align_batch(store: ReadStore, pairs, seeds, x=None, x_scalar=0, k=17, match=
     Returns dict(score int32 [n], beg int32 [n,2], end int32 [n,2],
     status int32 [n], cells int64 [n]) of device tensors (coordinates hold the
     uint32 bit patterns).  Asynchronous on `stream` (default: current).
-    tuning: dict(waves_per_cu, group_steps, order, x_tier1, x_tier2) for the
-    batched form (see xd_tuning).
+    tuning: dict(waves_per_cu, group_steps, order, x_tier1, x_tier2,
+    band_blocks) for the batched form (see xd_tuning).
     """
     n, out = _check_batch(pairs, seeds, x, out)
     lib = _lib.load()
@@ -220,6 +223,13 @@ def request_bytes(n: int) -> int:
     return int(_lib.load().xd_server_request_bytes(int(n)))
 
 
+def server_fixed_bytes(store, slots=0, tuning=None) -> int:
+    """Device bytes a server on this store holds whatever its load (each slot's
+    band-tier rows); requests share the rest of hbm_budget_bytes."""
+    cfg = _lib.ServerConfig(0, int(slots), 0, 0, 17, 1, -1, -1, _tuning_struct(tuning))
+    return int(_lib.load().xd_server_fixed_bytes(store.handle, ctypes.byref(cfg)))
+
+
 class Server:
     """Request server over a resident read store (xd_server).
 
@@ -230,12 +240,9 @@ class Server:
 
     def __init__(self, store, hbm_budget_bytes=0, slots=0, max_batch_tasks=0, max_pending=0,
                  k=17, match=1, mismatch=-1, gap=-1, tuning=None):
-        t = tuning or {}
         cfg = _lib.ServerConfig(int(hbm_budget_bytes), int(slots), int(max_batch_tasks),
                                 int(max_pending), int(k), int(match), int(mismatch), int(gap),
-                                _lib.Tuning(int(t.get("waves_per_cu", 0)),
-                                            int(t.get("group_steps", 0)), int(t.get("order", 0)),
-                                            int(t.get("x_tier1", 0)), int(t.get("x_tier2", 0))))
+                                _tuning_struct(tuning))
         h = ctypes.c_void_p()
         _lib.check(_lib.load().xd_server_create(store.handle, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -18,7 +18,7 @@ EXPORTS = (
     "xd_pack_reads", "xd_store_create", "xd_store_create_from_codes", "xd_store_destroy",
     "xd_store_info", "xd_align_batch", "xd_align_batch_persistent", "xd_plan_create",
     "xd_plan_launch", "xd_plan_destroy", "xd_profile_enable", "xd_profile_read",
-    "xd_server_request_bytes", "xd_server_create", "xd_server_submit", "xd_server_poll",
+    "xd_server_request_bytes", "xd_server_fixed_bytes", "xd_server_create", "xd_server_submit", "xd_server_poll",
     "xd_server_cancel", "xd_server_stats", "xd_server_destroy", "xd_last_error",
 )
 
@@ -26,7 +26,7 @@ EXPORTS = (
 class Tuning(ctypes.Structure):
     _fields_ = [("waves_per_cu", ctypes.c_int32), ("group_steps", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("x_tier1", ctypes.c_int32),
-                ("x_tier2", ctypes.c_int32)]
+                ("x_tier2", ctypes.c_int32), ("band_blocks", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -54,7 +54,7 @@ class ServerCounters(ctypes.Structure):
 class Profile(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_uint64), ("extensions", ctypes.c_uint64),
                 ("to_tier2", ctypes.c_uint64), ("to_tier3", ctypes.c_uint64),
-                ("to_tier4", ctypes.c_uint64),
+                ("to_tier4", ctypes.c_uint64), ("to_band", ctypes.c_uint64),
                 ("ms_tier1", ctypes.c_double), ("ms_wide", ctypes.c_double),
                 ("ms_combine", ctypes.c_double), ("ms_total", ctypes.c_double)]
 
@@ -103,6 +103,8 @@ def load() -> ctypes.CDLL:
     lib.xd_plan_destroy.restype = None
     lib.xd_server_request_bytes.argtypes = [u64]
     lib.xd_server_request_bytes.restype = u64
+    lib.xd_server_fixed_bytes.argtypes = [vp, ctypes.POINTER(ServerConfig)]
+    lib.xd_server_fixed_bytes.restype = u64
     lib.xd_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
     lib.xd_server_create.restype = ctypes.c_int
     lib.xd_server_submit.argtypes = [vp, vp, vp, vp, i32, u64, ctypes.POINTER(u64)]

@@ -11,6 +11,7 @@
 // worker thread does all device work; submit/poll only touch host state.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <atomic>
@@ -33,8 +34,10 @@ double now_s() {
 }
 
 // per task: pairs 8 + seeds 8 + x 4 in, score 4 + beg 8 + end 8 + status 4 +
-// cells 8 out; the batched form's scratch: 2 extensions x (24 + 16) bytes
-constexpr uint64_t kInBytes = 20, kOutBytes = 32, kScratchPerTask = 80;
+// cells 8 out; the batched form's scratch: 2 extensions x (24 + 5 lists x 4)
+// bytes; per batch the counters and tier arguments (the band tier's rows are
+// held per slot, outside the requests' share of the budget)
+constexpr uint64_t kInBytes = 20, kOutBytes = 32, kScratchPerTask = 88;
 constexpr uint64_t kBatchFixedBytes = 8192;
 
 struct Req {
@@ -67,6 +70,7 @@ struct Slot {
 
 // the library's error slot (xdrop.hip): xd_last_error() reports it
 int xd_internal_fail(int code, const char* msg);
+uint64_t xd_internal_band_bytes(uint32_t max_len, uint32_t blocks);
 
 struct xd_server {
   const xd_store* store = nullptr;
@@ -254,6 +258,15 @@ uint64_t xd_server_request_bytes(uint64_t n) {
   return n * (kInBytes + kOutBytes + kScratchPerTask) + kBatchFixedBytes;
 }
 
+uint64_t xd_server_fixed_bytes(const xd_store* store, const xd_server_config* cfg) {
+  if (!store || !cfg) return 0;
+  uint32_t max_len = 0;
+  if (xd_store_info(store, nullptr, nullptr, &max_len) != XD_OK) return 0;
+  const int32_t slots = cfg->slots <= 0 ? 4 : cfg->slots;
+  const uint32_t blocks = cfg->tuning.band_blocks > 0 ? (uint32_t)cfg->tuning.band_blocks : 1u;
+  return (uint64_t)slots * xd_internal_band_bytes(max_len, blocks);
+}
+
 int xd_server_create(const xd_store* store, const xd_server_config* cfg, xd_server** out) {
   if (!out || !store || !cfg) return set_err(XD_EINVAL, "xd_server_create: null argument");
   *out = nullptr;
@@ -264,11 +277,21 @@ int xd_server_create(const xd_store* store, const xd_server_config* cfg, xd_serv
   if (S->cfg.slots <= 0) S->cfg.slots = 4;
   if (S->cfg.max_batch_tasks <= 0) S->cfg.max_batch_tasks = 1 << 18;
   if (S->cfg.max_pending <= 0) S->cfg.max_pending = 1 << 16;
+  if (S->cfg.tuning.band_blocks <= 0) S->cfg.tuning.band_blocks = 1;
   if (S->cfg.slots > 64) {
     delete S;
     return set_err(XD_EINVAL, "xd_server_create: at most 64 slots");
   }
-  S->adm = new xd::AdmissionQueue(S->cfg.hbm_budget_bytes, S->cfg.slots,
+  const uint64_t fixed = xd_server_fixed_bytes(store, &S->cfg);
+  if (S->cfg.hbm_budget_bytes <= fixed + kBatchFixedBytes) {
+    delete S;
+    char msg[128];
+    snprintf(msg, sizeof(msg),
+             "xd_server_create: hbm_budget_bytes must exceed the fixed %llu bytes",
+             (unsigned long long)(fixed + kBatchFixedBytes));
+    return set_err(XD_EINVAL, msg);
+  }
+  S->adm = new xd::AdmissionQueue(S->cfg.hbm_budget_bytes - fixed, S->cfg.slots,
                                   (uint64_t)S->cfg.max_batch_tasks,
                                   (uint64_t)S->cfg.max_pending);
   S->slots.resize(S->cfg.slots);

@@ -3,13 +3,15 @@
 //
 // Windows ("tiers") of 64, 128, 256 and 1024 cells; an extension whose band
 // outgrows its window is appended to the next tier's overflow list and re-run
-// there from the start.
+// there from the start.  Past 1024 cells the band tier keeps the band in
+// global memory (one workgroup per extension), so no result is truncated.
 //
 // Plain form (xd_align_batch), stream-ordered on the caller's stream:
 //   k_reset      zero the counters and the histogram
 //   k_ext_first  one wavefront per extension (2 per task: left, right) with
 //                the 64-cell window
 //   k_ext_tier   persistent waves over the overflow lists of the wider tiers
+//   k_ext_band   persistent workgroups over what overflowed 1024 cells
 //   k_combine    one thread per task: status, seed score, score,
 //                coordinates, cells
 //
@@ -40,6 +42,9 @@ namespace {
 constexpr uint32_t kWideBlocks = 2048;
 constexpr int kCostBins = 128;          // per tier
 constexpr int kBins = 4 * kCostBins;    // tier-major
+constexpr int kBandWaves = 16;          // waves per band-tier workgroup
+constexpr uint32_t kBandBlocksMax = 16;
+constexpr uint64_t kBandBudget = 64ull << 20;  // default band area per batch
 
 struct StoreDev {
   const uint32_t* words;
@@ -65,40 +70,67 @@ struct BatchArgs {
   uint64_t* cells;
 };
 
+// Band tier geometry: each workgroup owns three rows of cap words, cap >
+// the longest read of the store.
+struct BandGeom {
+  int32_t cap;
+  uint32_t blocks;
+};
+
+BandGeom band_geom(uint32_t max_len, uint32_t blocks) {
+  BandGeom b;
+  b.cap = (int32_t)(((uint64_t)max_len + 1 + 63) & ~63ull);
+  if (!blocks) {
+    const uint64_t fit = kBandBudget / (12ull * (uint64_t)b.cap);
+    blocks = (uint32_t)(fit < 1 ? 1 : fit > kBandBlocksMax ? kBandBlocksMax : fit);
+  }
+  b.blocks = blocks;
+  return b;
+}
+
+uint64_t band_bytes(const BandGeom& b) { return (uint64_t)b.blocks * 12ull * (uint64_t)b.cap; }
+
 // Device scratch of one batch.
 struct Scratch {
   ExtOut* ext;        // [2n]
   uint32_t* queue;    // [2n] extension ids: tier-major, longest first
-  uint32_t* ovf[3];   // [2n] each: overflow of tier t into tier t+1
+  uint32_t* ovf[4];   // [2n] each: overflow of tier t into tier t+1 (3: band)
   uint32_t* hist;     // [kBins] histogram, then running cursors
   uint32_t* ctr;      // [32] counters, see below
-  void* targs;        // [4] TierArgs of the four tiers
+  void* targs;        // [5] TierArgs of the four windows and the band tier
+  int32_t* band;      // [blocks][3][cap] rows of the band tier
+  BandGeom geom;
 };
 // ctr layout
-constexpr int kOvfCount = 0;   // [0..2] sizes of ovf[0..2]
+constexpr int kOvfCount = 0;   // [0..3] sizes of ovf[0..3]
 constexpr int kHead = 4;       // [4..7] work heads of tiers 0..3
 constexpr int kSeg = 8;        // [8..12] queue start of tiers 0..3, then 2n
+constexpr int kBandHead = 13;  // work head of the band tier
 constexpr int kCtrWords = 32;
-constexpr int kTierArgsBytes = 4 * 256;  // >= 4 * sizeof(TierArgs), checked below
+constexpr int kTierArgsBytes = 5 * 256;  // >= 5 * sizeof(TierArgs), checked below
+constexpr uint64_t kFixedBytes = (kBins * 4 + kCtrWords * 4 + kTierArgsBytes + 255) & ~255ull;
 
-uint64_t scratch_bytes(uint64_t n) {
+uint64_t scratch_bytes(uint64_t n, const BandGeom& g) {
   const uint64_t n_ext = 2 * n;
   const uint64_t ext = (n_ext * sizeof(ExtOut) + 255) & ~255ull;
   const uint64_t list = (n_ext * 4 + 255) & ~255ull;
-  return ext + 4 * list + kBins * 4 + kCtrWords * 4 + kTierArgsBytes;
+  return ext + 5 * list + kFixedBytes + band_bytes(g);
 }
 
-Scratch scratch_carve(char* base, uint64_t n) {
+Scratch scratch_carve(char* base, uint64_t n, const BandGeom& g) {
   const uint64_t n_ext = 2 * n;
   const uint64_t ext = (n_ext * sizeof(ExtOut) + 255) & ~255ull;
   const uint64_t list = (n_ext * 4 + 255) & ~255ull;
   Scratch s;
   s.ext = (ExtOut*)base;
   s.queue = (uint32_t*)(base + ext);
-  for (int q = 0; q < 3; ++q) s.ovf[q] = (uint32_t*)(base + ext + (1 + q) * list);
-  s.hist = (uint32_t*)(base + ext + 4 * list);
-  s.ctr = (uint32_t*)(base + ext + 4 * list + kBins * 4);
-  s.targs = base + ext + 4 * list + kBins * 4 + kCtrWords * 4;
+  for (int q = 0; q < 4; ++q) s.ovf[q] = (uint32_t*)(base + ext + (1 + q) * list);
+  char* fixed = base + ext + 5 * list;
+  s.hist = (uint32_t*)fixed;
+  s.ctr = (uint32_t*)(fixed + kBins * 4);
+  s.targs = fixed + kBins * 4 + kCtrWords * 4;
+  s.band = (int32_t*)(fixed + kFixedBytes);
+  s.geom = g;
   return s;
 }
 
@@ -114,11 +146,11 @@ struct TierArgs {
   uint32_t* out_count;
 };
 
-static_assert(4 * sizeof(TierArgs) <= kTierArgsBytes, "tier argument area");
+static_assert(5 * sizeof(TierArgs) <= kTierArgsBytes, "tier argument area");
 static_assert(sizeof(TierArgs) % 4 == 0, "tier arguments copied by words");
 
 struct TierPack {
-  TierArgs t[4];
+  TierArgs t[5];
 };
 
 // ---- per-task validation (shared by the extension and combine kernels) ----
@@ -151,10 +183,8 @@ __device__ __forceinline__ void ext_lengths(const BatchArgs& A, uint32_t e, uint
   }
 }
 
-// Sets up and runs extension e on the calling wave.  Returns false if it
-// overflowed this tier's window.
-template <int CPL, int GS, bool UNIT>
-__device__ __forceinline__ bool run_ext(const BatchArgs& A, uint32_t e, uint32_t* ring) {
+// Inputs of extension e (wave-uniform); false if its task is invalid.
+__device__ __forceinline__ bool make_ext(const BatchArgs& A, uint32_t e, xd::Ext& ex) {
   const uint32_t t = e >> 1;
   uint32_t ra, rb, pa, pb;
   int32_t X;
@@ -164,16 +194,9 @@ __device__ __forceinline__ bool run_ext(const BatchArgs& A, uint32_t e, uint32_t
   pa = __builtin_amdgcn_readfirstlane(pa);
   pb = __builtin_amdgcn_readfirstlane(pb);
   X = __builtin_amdgcn_readfirstlane(X);
-  if (__builtin_amdgcn_readfirstlane(st) != XD_TASK_OK) {
-    if (xd::lane_id() == 0) {
-      ExtOut o = {0, 0, 0, xd::kExtInvalid, 0};
-      A.ext[e] = o;
-    }
-    return true;
-  }
+  if (__builtin_amdgcn_readfirstlane(st) != XD_TASK_OK) return false;
   const int32_t la = (int32_t)__builtin_amdgcn_readfirstlane(A.st.len[ra]);
   const int32_t lb = (int32_t)__builtin_amdgcn_readfirstlane(A.st.len[rb]);
-  xd::Ext ex;
   ex.wa = A.st.words + A.st.word_off[ra];
   ex.wb = A.st.words + A.st.word_off[rb];
   ex.X = X;
@@ -186,6 +209,21 @@ __device__ __forceinline__ bool run_ext(const BatchArgs& A, uint32_t e, uint32_t
     ex.oa = (int32_t)pa - 1;
     ex.ob = (int32_t)pb - 1;
     ex.dir = -1;
+  }
+  return true;
+}
+
+// Sets up and runs extension e on the calling wave.  Returns false if it
+// overflowed this tier's window.
+template <int CPL, int GS, bool UNIT>
+__device__ __forceinline__ bool run_ext(const BatchArgs& A, uint32_t e, uint32_t* ring) {
+  xd::Ext ex;
+  if (!make_ext(A, e, ex)) {
+    if (xd::lane_id() == 0) {
+      ExtOut o = {0, 0, 0, xd::kExtInvalid, 0};
+      A.ext[e] = o;
+    }
+    return true;
   }
   ExtOut o;
   if (!xd::extend<CPL, GS, UNIT>(ex, A.sc, ring, o)) return false;
@@ -254,6 +292,34 @@ __global__ __launch_bounds__(64 * WAVES) void k_ext_tier(const TierArgs* __restr
         R.A.ext[e] = o;
       }
     }
+  }
+}
+
+// Band tier: persistent workgroups of kBandWaves waves, each taking the next
+// extension of in_list (what overflowed the 1024-cell window) and running it
+// with its rows in its own part of band.
+__global__ __launch_bounds__(64 * kBandWaves) void k_ext_band(const TierArgs* __restrict__ P,
+                                                              int32_t* __restrict__ band,
+                                                              int32_t cap) {
+  __shared__ xd::BandPart part[2 * kBandWaves];
+  __shared__ uint64_t csum[kBandWaves];
+  __shared__ uint32_t item;
+  int32_t* buf = band + (uint64_t)blockIdx.x * 3ull * (uint64_t)cap;
+  const TierArgs& Q = *P;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const uint32_t n_in = *Q.in_count;
+      const uint32_t idx = atomicAdd(Q.head, 1u);
+      item = idx < n_in ? Q.in_list[idx] : 0xffffffffu;
+    }
+    __syncthreads();
+    const uint32_t e = item;
+    __syncthreads();  // item is read before thread 0 takes the next one
+    if (e == 0xffffffffu) break;
+    xd::Ext ex;
+    ExtOut o = {0, 0, 0, xd::kExtInvalid, 0};
+    if (make_ext(Q.A, e, ex)) xd::extend_band<kBandWaves>(ex, Q.A.sc, buf, cap, part, csum, o);
+    if (threadIdx.x == 0) Q.A.ext[e] = o;
   }
 }
 
@@ -357,7 +423,7 @@ __global__ __launch_bounds__(256) void k_combine(BatchArgs A) {
 // ---- launch sequences -------------------------------------------------------
 
 struct Tuned {
-  int waves_per_cu, group_steps, order, x_tier1, x_tier2;
+  int waves_per_cu, group_steps, order, x_tier1, x_tier2, band_blocks;
 };
 
 int device_cus() {
@@ -383,7 +449,8 @@ TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
   p.t[2] = {A, S.queue, segs ? c + kSeg + 2 : nullptr, S.ovf[1], c + kOvfCount + 1,
             c + kHead + 2, S.ovf[2], c + kOvfCount + 2};
   p.t[3] = {A, S.queue, segs ? c + kSeg + 3 : nullptr, S.ovf[2], c + kOvfCount + 2,
-            c + kHead + 3, nullptr, nullptr};
+            c + kHead + 3, S.ovf[3], c + kOvfCount + 3};
+  p.t[4] = {A, S.queue, nullptr, S.ovf[3], c + kOvfCount + 3, c + kBandHead, nullptr, nullptr};
   return p;
 }
 
@@ -394,6 +461,8 @@ void launch_wide(const Scratch& S, uint32_t blocks, hipStream_t stream) {
   hipLaunchKernelGGL((k_ext_tier<4, 4, UNIT, 4>), dim3(blocks), dim3(256), 0, stream, ta + 2);
   hipLaunchKernelGGL((k_ext_tier<16, 2, UNIT, 1>), dim3(4 * blocks), dim3(64), 0, stream,
                      ta + 3);
+  hipLaunchKernelGGL(k_ext_band, dim3(S.geom.blocks), dim3(64 * kBandWaves), 0, stream, ta + 4,
+                     S.band, S.geom.cap);
 }
 
 template <bool UNIT>
@@ -479,6 +548,7 @@ int check_tuning(const xd_tuning* t, Tuned& out) {
   out.order = 1;
   out.x_tier1 = 32;
   out.x_tier2 = 80;
+  out.band_blocks = 0;
   if (!t) return XD_OK;
   if (t->waves_per_cu) {
     if (t->waves_per_cu < 4 || t->waves_per_cu > 32 || t->waves_per_cu % 4)
@@ -498,6 +568,9 @@ int check_tuning(const xd_tuning* t, Tuned& out) {
   if (t->x_tier2) out.x_tier2 = t->x_tier2;
   if (out.x_tier1 < 0 || out.x_tier2 < out.x_tier1)
     return fail(XD_EINVAL, "need 0 <= x_tier1 <= x_tier2");
+  if (t->band_blocks < 0 || t->band_blocks > 1024)
+    return fail(XD_EINVAL, "band_blocks must be in [0, 1024]");
+  out.band_blocks = t->band_blocks;
   return XD_OK;
 }
 
@@ -609,10 +682,12 @@ int enqueue(BatchArgs A, const Scratch& S, bool persistent, const Tuned& tu,
   return XD_OK;
 }
 
-int batch_async(const BatchArgs& A, bool persistent, const Tuned& tu, hipStream_t stream) {
+int batch_async(const BatchArgs& A, uint32_t max_len, bool persistent, const Tuned& tu,
+                hipStream_t stream) {
+  const BandGeom g = band_geom(max_len, (uint32_t)tu.band_blocks);
   char* mem = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&mem, scratch_bytes(A.n), stream));
-  int rc = enqueue(A, scratch_carve(mem, A.n), persistent, tu, stream, true);
+  HIP_TRY(hipMallocAsync((void**)&mem, scratch_bytes(A.n, g), stream));
+  int rc = enqueue(A, scratch_carve(mem, A.n, g), persistent, tu, stream, true);
   hipError_t fe = hipFreeAsync(mem, stream);
   if (rc) return rc;
   if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
@@ -625,6 +700,13 @@ int batch_async(const BatchArgs& A, bool persistent, const Tuned& tu, hipStream_
 __attribute__((visibility("hidden"))) int xd_internal_fail(int code, const char* msg) {
   g_err = msg ? msg : "";
   return code;
+}
+
+// device bytes of the band tier's rows for a store whose longest read has
+// max_len bases, with `blocks` workgroups (0 = the default count)
+__attribute__((visibility("hidden"))) uint64_t xd_internal_band_bytes(uint32_t max_len,
+                                                                      uint32_t blocks) {
+  return band_bytes(band_geom(max_len, blocks));
 }
 
 extern "C" {
@@ -747,7 +829,7 @@ int xd_align_batch(const xd_store* store, const uint32_t* pairs, const uint32_t*
   if (n == 0) return XD_OK;
   Tuned tu;
   check_tuning(nullptr, tu);
-  return batch_async(A, false, tu, (hipStream_t)hip_stream);
+  return batch_async(A, store->max_len, false, tu, (hipStream_t)hip_stream);
 }
 
 int xd_align_batch_persistent(const xd_store* store, const uint32_t* pairs,
@@ -764,7 +846,7 @@ int xd_align_batch_persistent(const xd_store* store, const uint32_t* pairs,
   rc = check_tuning(tuning, tu);
   if (rc) return rc;
   if (n == 0) return XD_OK;
-  return batch_async(A, true, tu, (hipStream_t)hip_stream);
+  return batch_async(A, store->max_len, true, tu, (hipStream_t)hip_stream);
 }
 
 int xd_plan_create(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,
@@ -783,8 +865,9 @@ int xd_plan_create(const xd_store* store, const uint32_t* pairs, const uint32_t*
   if (rc) return rc;
   xd_plan* p = new xd_plan();
   p->args = A;
+  const BandGeom g = band_geom(store->max_len, (uint32_t)tu.band_blocks);
   hipError_t e = hipGetDevice(&p->device);
-  if (e == hipSuccess) e = hipMalloc((void**)&p->mem, scratch_bytes(n));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->mem, scratch_bytes(n, g));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -792,7 +875,7 @@ int xd_plan_create(const xd_store* store, const uint32_t* pairs, const uint32_t*
     xd_plan_destroy(p);
     return rc;
   }
-  p->scratch = scratch_carve(p->mem, n);
+  p->scratch = scratch_carve(p->mem, n, g);
   e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) {
     rc = hip_fail(e, "hipStreamBeginCapture");
@@ -854,6 +937,7 @@ int xd_profile_read(xd_profile* out, int reset) {
     g_prof_sum.to_tier2 += r.counters[kOvfCount + 0];
     g_prof_sum.to_tier3 += r.counters[kOvfCount + 1];
     g_prof_sum.to_tier4 += r.counters[kOvfCount + 2];
+    g_prof_sum.to_band += r.counters[kOvfCount + 3];
     g_prof_sum.ms_tier1 += t1;
     g_prof_sum.ms_wide += t2;
     g_prof_sum.ms_combine += t3;

@@ -426,4 +426,156 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
   return true;
 }
 
+// ---- band in global memory ---------------------------------------------
+//
+// Last resort for bands wider than every register window: one workgroup of
+// NW waves runs the extension with antidiagonals d-2, d-1 and d held as
+// three rows of cap >= m+1 words in global memory (indexed by row i; the
+// three rows rotate).  Each antidiagonal's candidate rows are swept 64*NW at
+// a time; the live range, the new best and its row are reduced through LDS
+// and one barrier per antidiagonal orders the rows.  Same rule and same U
+// representation as the register windows, so the results are the same.
+
+struct BandPart {
+  int32_t lo, hi;    // live rows of the antidiagonal seen by one wave
+  int32_t best, bi;  // largest improving U (0: none) and its smallest row
+};
+
+__device__ __forceinline__ uint64_t wave_sum_u64v(uint64_t s) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)s, off, 64);
+    const uint32_t hi = __shfl_xor((uint32_t)(s >> 32), off, 64);
+    s += ((uint64_t)hi << 32) | lo;
+  }
+  return s;
+}
+
+// Called by all 64*NW threads of the workgroup.  part: LDS [2*NW];
+// csum: LDS [NW].  res is set in every thread.
+template <int NW>
+__device__ __forceinline__ void extend_band(const Ext& e, const Scoring& sc,
+                                            int32_t* __restrict__ buf, int32_t cap,
+                                            BandPart* part, uint64_t* csum, ExtOut& res) {
+  const int tid = (int)threadIdx.x;
+  const int w = tid >> 6, lane = tid & 63;
+  const int32_t g = -sc.G;
+  const int32_t C = sc.MM + 2 * g;
+  const int32_t dM = sc.M - sc.MM;
+  const int32_t X = e.X;
+  const int32_t bias = X + kBias0;
+  const int32_t m = e.m, n = e.n;
+  int32_t* r0 = buf;            // antidiagonal d+1 (being computed)
+  int32_t* r1 = buf + cap;      // d
+  int32_t* r2 = buf + 2 * cap;  // d-1
+  // written and live row ranges of antidiagonals d (..1) and d-1 (..2)
+  int32_t wlo1 = 0, whi1 = 0, llo1 = 0, lhi1 = 0;
+  int32_t wlo2 = 0, whi2 = -1, llo2 = 0, lhi2 = -1;
+  if (tid == 0) r1[0] = bias;  // antidiagonal 0: the origin, U(0,0) = bias
+  __syncthreads();
+  int32_t thr = g + kBias0;  // T_d - X + g*(d+1) + bias
+  int32_t bi = 0, dstar = 0;
+  uint64_t cnt = 0;
+  int32_t d = 0;
+  int par = 0;
+  for (;;) {
+    const bool live1 = llo1 <= lhi1, live2 = llo2 <= lhi2;
+    if ((!live1 && !live2) || d >= m + n) break;
+    const int32_t dn = d + 1;
+    // rows of dn with a predecessor in a live range: left/up from d,
+    // diagonal from d-1, inside the grid
+    int32_t clo = 0x7fffffff, chi = -1;
+    if (live1) {
+      clo = min(clo, llo1);
+      chi = max(chi, lhi1 + 1);
+    }
+    if (live2) {
+      clo = min(clo, llo2 + 1);
+      chi = max(chi, lhi2 + 1);
+    }
+    clo = max(clo, max(0, dn - n));
+    chi = min(chi, min(m, dn));
+    const int32_t timp = thr + X;
+    int32_t plo = 0x7fffffff, phi = -1, pbest = 0, pbi = -1;
+    for (int32_t i0 = clo + 64 * w; i0 <= chi; i0 += 64 * NW) {
+      const int32_t i = i0 + lane;
+      const bool act = i <= chi;
+      int32_t s = 0;
+      if (act) {
+        const int32_t j = dn - i;
+        const int32_t up = (i - 1 >= wlo1 && i - 1 <= whi1) ? r1[i - 1] : 0;
+        const int32_t left = (i >= wlo1 && i <= whi1) ? r1[i] : 0;
+        const int32_t dg = (i - 1 >= wlo2 && i - 1 <= whi2) ? r2[i - 1] : 0;
+        int32_t bonus = 0;
+        if (i >= 1 && j >= 1 &&
+            code_at(e.wa, e.oa + e.dir * (i - 1)) == code_at(e.wb, e.ob + e.dir * (j - 1)))
+          bonus = dM;
+        s = max(max(dg + bonus + C, up), left);
+        cnt += (s > kEvMin) ? 1u : 0u;
+        r0[i] = s >= thr ? s : 0;
+      }
+      const bool lv = act && s >= thr;
+      const uint64_t lm = ballot64(lv);
+      if (lm) {
+        plo = min(plo, i0 + (int32_t)__builtin_ctzll(lm));
+        phi = max(phi, i0 + 63 - (int32_t)__builtin_clzll(lm));
+      }
+      const bool im = act && s > timp;
+      if (ballot64(im)) {
+        const int32_t v = __builtin_amdgcn_readfirstlane(wave_max_i32(im ? s : 0));
+        if (v > pbest) {  // rows rise with i0: keep the first row reaching v
+          pbest = v;
+          pbi = i0 + (int32_t)__builtin_ctzll(ballot64(im && s == v));
+        }
+      }
+    }
+    if (lane == 0) part[par * NW + w] = {plo, phi, pbest, pbi};
+    __syncthreads();  // rows of dn and the parts are complete
+    int32_t llo0 = 0x7fffffff, lhi0 = -1, best = 0, best_i = 0x7fffffff;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      const BandPart P = part[par * NW + q];
+      llo0 = min(llo0, P.lo);
+      lhi0 = max(lhi0, P.hi);
+      if (P.best > best) {
+        best = P.best;
+        best_i = P.bi;
+      } else if (P.best == best && P.best > 0) {
+        best_i = min(best_i, P.bi);
+      }
+    }
+    if (best > 0) {  // T rises to the new best, first reached at row best_i
+      thr += best - timp;
+      bi = best_i;
+      dstar = dn;
+    }
+    thr += g;
+    int32_t* t = r2;
+    r2 = r1;
+    r1 = r0;
+    r0 = t;
+    wlo2 = wlo1;
+    whi2 = whi1;
+    llo2 = llo1;
+    lhi2 = lhi1;
+    wlo1 = clo;
+    whi1 = chi;
+    llo1 = llo0;
+    lhi1 = lhi0;
+    d = dn;
+    par ^= 1;
+  }
+  const uint64_t wc = wave_sum_u64v(cnt);
+  if (lane == 0) csum[w] = wc;
+  __syncthreads();
+  uint64_t cells = 0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) cells += csum[q];
+  __syncthreads();  // csum and part are free for the next extension
+  res.best = thr + X - g * (d + 1) - bias;
+  res.bi = bi;
+  res.bj = dstar - bi;
+  res.flags = kExtDone;
+  res.cells = cells;
+}
+
 }  // namespace xd

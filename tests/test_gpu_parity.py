@@ -144,18 +144,61 @@ def test_edge_cases():
     assert_same(got, ref, label="edge")
 
 
-def test_band_overflow_reports_status():
-    # identical 3 kbp reads with a huge X need a band wider than 1024 cells
+def band_workload():
+    """Extensions whose live band outgrows the 1024-cell window, beside narrow ones."""
     rng = np.random.default_rng(9)
     A = rand_codes(rng, 3000)
-    w = workload_from([A, A.copy()], [(0, 1, 1500, 1500, 4000), (0, 1, 1500, 1500, 25)])
-    got = run_gpu(w)
+    L = rand_codes(rng, 20000)
+    R1, R2 = rand_codes(rng, 5000), rand_codes(rng, 5000)
+    M = mutate_codes(rng, A, 0.15)
+    reads = [A, A.copy(), L, L.copy(), R1, R2, M]
+    tasks = [(0, 1, 1500, 1500, 4000),         # identical, band grows to the read ends
+             (0, 1, 1500, 1500, 25),           # same pair, narrow
+             (2, 3, 10000, 10000, 2000),       # identical 20 kbp, ~2700-cell band
+             (4, 5, 2500, 2500, 1 << 20),      # unrelated reads, no pruning: full grid
+             (0, 6, 1000, 1000, 1500),         # 15 % mutated copy, wide X
+             (2, 3, 0, 19000, 1 << 20),        # seed at both read ends
+             (0, 1, 0, 0, 3000)]
+    return workload_from(reads, tasks)
+
+
+@pytest.mark.parametrize("form", ["plain", "persistent", "persistent1", "plan"])
+def test_band_tier_parity(form):
+    # bands wider than 1024 cells run in the band tier: same results as the oracle
+    w = band_workload()
+    print("band tier", form, flush=True)
     ref = oracle.align_workload(w)
-    if got["status"][0] == xd.TASK_BAND_OVERFLOW:
-        assert got["score"][0] == np.iinfo(np.int32).min and got["cells"][0] == 0
-        assert_same({k: v[1:] for k, v in got.items()}, {k: v[1:] for k, v in ref.items()})
+    xd.profile_enable(True)
+    xd.profile_read(reset=True)
+    store = xd.ReadStore.from_workload(w)
+    pairs, seeds, xs = xd.workload_tensors(w, "cuda")
+    if form == "plan":
+        plan = xd.Plan(store, pairs, seeds, x=xs, k=w.k)
+        out = plan.launch()
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        plan.close()
     else:
-        assert_same(got, ref, label="wide")
+        tuning = dict(band_blocks=1) if form == "persistent1" else None
+        out = xd.align_batch(store, pairs, seeds, x=xs, k=w.k, persistent=form != "plain",
+                             tuning=tuning)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+    prof = xd.profile_read(reset=True)
+    xd.profile_enable(False)
+    store.close()
+    assert (ref["status"] == 0).all()
+    assert_same(got, ref, label="band " + form)
+    if form != "plan":  # plans record no profile
+        assert prof["to_band"] >= 6, prof
+
+
+def test_band_tier_scoring():
+    w = band_workload().subset(np.array([0, 4, 6]))
+    for (M, MM, G) in ((2, -3, -2), (5, -4, -7)):
+        got = run_gpu(w, match=M, mismatch=MM, gap=G)
+        assert_same(got, oracle.align_workload(w, match=M, mismatch=MM, gap=G),
+                    label="band %s" % ((M, MM, G),))
 
 
 def test_empty_batch():

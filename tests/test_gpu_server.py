@@ -50,7 +50,8 @@ def test_server_mix_equals_alone():
     reqs = make_requests(w, rng, 80, 600)
     store = xd.ReadStore.from_workload(w)
     ref = [alone(store, p, s, X, w.k) for (p, s, X) in reqs]
-    budget = 4 * xd.request_bytes(600)
+    fixed = xd.server_fixed_bytes(store, slots=3)
+    budget = fixed + 4 * xd.request_bytes(600)
     srv = xd.Server(store, hbm_budget_bytes=budget, slots=3, max_batch_tasks=900, k=w.k)
     ids = []
     for q, (p, s, X) in enumerate(reqs):
@@ -64,7 +65,7 @@ def test_server_mix_equals_alone():
         assert same(g, r), "request %d differs from its solo run" % q
         assert g["info"]["t_done"] >= g["info"]["t_start"] >= g["info"]["t_submit"]
     assert st["completed"] == len(reqs)
-    assert st["peak_inflight_bytes"] <= budget
+    assert st["peak_inflight_bytes"] <= budget - fixed
     assert st["batches"] < len(reqs)          # requests were packed together
     assert st["peak_busy_slots"] >= 2         # batches overlapped on the device
     # and the solo runs agree with the oracle on a sample
@@ -78,7 +79,11 @@ def test_server_mix_equals_alone():
 def test_server_cancel_zero_and_oversize():
     w = synth.config("c5-small")
     store = xd.ReadStore.from_workload(w)
-    srv = xd.Server(store, hbm_budget_bytes=xd.request_bytes(300), slots=1, k=w.k)
+    fixed = xd.server_fixed_bytes(store, slots=1)
+    assert fixed > 0
+    with pytest.raises(xd.XdropError):  # nothing left for requests
+        xd.Server(store, hbm_budget_bytes=fixed, slots=1, k=w.k)
+    srv = xd.Server(store, hbm_budget_bytes=fixed + xd.request_bytes(300), slots=1, k=w.k)
     p = np.stack([w.ra[:300], w.rb[:300]], 1)
     s = np.stack([w.pa[:300], w.pb[:300]], 1)
     a = srv.submit(p, s, x_scalar=25)
