@@ -167,6 +167,43 @@ __device__ __forceinline__ void unit_improve(uint64_t imp, int32_t g, int32_t& t
   lastt = lt;
 }
 
+// acc + (bit `lane` of mask), one vector add with the mask as carry-in
+__device__ __forceinline__ uint32_t add_lane_bit(uint32_t acc, uint64_t mask) {
+  uint32_t r;
+  uint64_t carry_out;
+  asm("v_addc_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(r), "=s"(carry_out) : "v"(acc), "s"(mask));
+  return r;
+}
+
+// leading zeros of a 64-bit scalar mask, -1 for 0 (s_flbit_i32_b64)
+__device__ __forceinline__ int32_t sclz64(uint64_t v) {
+  int32_t r;
+  asm("s_flbit_i32_b64 %0, %1" : "=s"(r) : "s"(v));
+  return r;
+}
+
+// trailing zeros of a 64-bit scalar mask, -1 for 0 (s_ff1_i32_b64)
+__device__ __forceinline__ int32_t sctz64(uint64_t v) {
+  int32_t r;
+  asm("s_ff1_i32_b64 %0, %1" : "=s"(r) : "s"(v));
+  return r;
+}
+
+// imp[K] for the largest K <= T with imp[K] != 0 (K + 1 in kk), or kk = 0;
+// tested from the last step down, so the scan stops at the first hit
+template <int T, int G>
+__device__ __forceinline__ void last_nonzero(const uint64_t (&imp)[G], uint64_t& mask,
+                                             int32_t& kk) {
+  if constexpr (T >= 0) {
+    if (imp[T]) {
+      mask = imp[T];
+      kk = T + 1;
+    } else {
+      last_nonzero<T - 1, G>(imp, mask, kk);
+    }
+  }
+}
+
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
@@ -358,8 +395,98 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
     d += G;
   };
 
+  // A full group clear of the walls, for match == 1 and one cell per lane
+  // (the 64-cell window).  Inside the grid a cell is evaluated iff its left,
+  // up or diagonal predecessor is live, so antidiagonal d+1's evaluated
+  // lanes are also L_d | (L_d | L_{d-1}) << 1 from the live masks, added to
+  // the lane counts with the mask as carry-in: one vector instruction and
+  // three scalar ones instead of two vector ones.  Every other step counts
+  // that way, which balances the vector and scalar issue rates.  Each
+  // step's improving mask stays in a scalar register; the arg-max is taken
+  // once after the group from the last step that improved (T rose by 1 on
+  // exactly those steps).
+  auto group_unit1 = [&](auto len_tag) {
+    constexpr int G = decltype(len_tag)::value;
+    const int32_t r = (d + 1 - base - lane) & MASK;
+    const uint8_t* rbytes = (const uint8_t*)ring;
+    const uint32_t ad = ((uint32_t)r << 2) + aa[0];
+    uint32_t bmv[G];
+#pragma unroll
+    for (int t = 0; t < G; ++t) bmv[t] = rbytes[ad + 4 * t];
+    uint64_t imp[G];
+    uint64_t Ld = Lc[0], Lm = Lp[0];
+    const int32_t thr0 = thr;
+    auto body = [&](auto t_tag) {
+      constexpr int t = decltype(t_tag)::value;
+      const int32_t timp = thr + X;
+      const int32_t upv = shr1_zero(U1[0]);
+      const int32_t s = max(max(Up[0] + (int32_t)bmv[t] + C, upv), U1[0]);
+      if constexpr ((t & 1) == 0)
+        cnt = add_lane_bit(cnt, Ld | ((Ld | Lm) << 1));
+      else
+        cnt += (s > kEvMin) ? 1u : 0u;
+      const bool lv = s >= thr;
+      const uint64_t L = ballot64(lv);
+      imp[t] = ballot64(s > timp);
+      Up[0] = upv;
+      U1[0] = lv ? s : 0;
+      thr = add_nonzero(thr, g, imp[t]);
+      Lm = Ld;
+      Ld = L;
+    };
+    static_for<G>(body);
+    Lc[0] = Ld;
+    Lp[0] = Lm;
+    if (thr != thr0 + G * g) {
+      uint64_t lm = 0;
+      int32_t kk = 0;
+      last_nonzero<G - 1, G>(imp, lm, kk);
+      bi = base + sctz64(lm);
+      dstar = d + kk;
+    }
+    d += G;
+  };
+
   bool overflow = false;
   for (;;) {
+    if constexpr (UNIT && CPL == 1) {
+      // the common case in one test: a full group fits below the window top
+      // (hi + GS <= 63, which also needs a live cell), the grid is not done,
+      // the ring holds the group's b, and the band stays clear of both walls
+      // (d < m+n follows from the two wall conditions)
+      const uint64_t M = Lc[0] | Lp[0];
+      const int32_t z = sclz64(M);  // 63 - hi
+      const int32_t lo = sctz64(M);
+      const int32_t dv = d - base;
+      const int32_t c = (z - GS) | (z + (m - base - 63 - GS)) | (lo - dv + (n - GS)) |
+                        (filled - dv - GS);
+      if (c >= 0) {
+        group_unit1(std::integral_constant<int, GS>{});
+        continue;
+      }
+      // the two usual reasons it fails, handled here and tested again: the
+      // band nears the window top (slide the window up to its lowest live
+      // row), or the ring needs its next chunk of b
+      if (M != 0 && (m + n - 1 - d) >= 0) {
+        if (z < GS && lo > 0) {
+          const int src = lane + lo;
+          const bool inside = src < 64;
+          const int32_t u1 = __builtin_amdgcn_ds_bpermute((src & 63) << 2, U1[0]);
+          const int32_t up = __builtin_amdgcn_ds_bpermute((src & 63) << 2, Up[0]);
+          U1[0] = inside ? u1 : 0;
+          Up[0] = inside ? up : 0;
+          Lc[0] >>= lo;
+          Lp[0] >>= lo;
+          base += lo;
+          load_a();
+          continue;
+        }
+        if (filled < dv + GS) {
+          fill_to(d + GS - base);
+          continue;
+        }
+      }
+    }
     int32_t lo = Q, hi = -1;
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
@@ -403,16 +530,24 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
     const int32_t room_a = m - base - hi, room_b = base + lo - d + n;
     if (full) {
       const bool fast = ((room_a - GS) | (room_b - GS)) >= 0;
-      if (fast)
-        group(std::false_type{}, std::integral_constant<int, GS>{});
-      else
+      if (fast) {
+        if constexpr (UNIT && CPL == 1)
+          group_unit1(std::integral_constant<int, GS>{});
+        else
+          group(std::false_type{}, std::integral_constant<int, GS>{});
+      } else {
         group(std::true_type{}, std::integral_constant<int, GS>{});
+      }
     } else {
       const bool fast = ((room_a - kShort) | (room_b - kShort)) >= 0;
-      if (fast)
-        group(std::false_type{}, std::integral_constant<int, kShort>{});
-      else
+      if (fast) {
+        if constexpr (UNIT && CPL == 1)
+          group_unit1(std::integral_constant<int, kShort>{});
+        else
+          group(std::false_type{}, std::integral_constant<int, kShort>{});
+      } else {
         group(std::true_type{}, std::integral_constant<int, kShort>{});
+      }
     }
   }
   if (overflow) return false;
