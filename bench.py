@@ -30,7 +30,7 @@ METRIC = "GCUPS and aligned pairs/sec for X-drop extension at X=25 (1 MI355X)"
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
 OPS_PER_CELL = 8  # compare, select, add diagonal, max(up,left), add gap, max, compare, select
 KERNEL_NAMES = {"plain": "k_ext_first<1, 16, true>",
-                "persistent": "k_ext_list<1, GS, true, 4> (64-cell tier, queue)"}
+                "persistent": "k_ext_tier<1, GS, true, 4> (64-cell tier, queue)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
 
 WORKLOAD_DESC = {
@@ -40,6 +40,10 @@ WORKLOAD_DESC = {
     "c1": ("c1: 1,000 read pairs, 200 kbp genome, reads 2-5 kbp, 5/5/5% errors, X=7, +1/-1/-1"),
     "c3": ("c3: 2,000,000 (pair, seed) tasks over the c2 read set (true seeds >= 17 apart), "
            "X uniform in {7, 25, 50}, +1/-1/-1"),
+    "c4": ("c4: 20,000,000 (pair, seed) tasks, 100 Mbp genome (90 Mbp uniform + 2,000 copies "
+           "of 200 random 5 kbp segments) at 30x, read lengths log-normal mean 12 kbp sd 6 kbp "
+           "clipped 1-60 kbp, 4/4/4% errors, 10% of tasks from reads over different repeat "
+           "copies, X=25, +1/-1/-1"),
 }
 
 
@@ -211,7 +215,8 @@ def main():
                 "cells_per_launch": cells_per_step, "ops_per_cell": OPS_PER_CELL,
                 "kernel_gcups": round(cells_per_step / (k_ms / 1e3) / 1e9, 2),
                 "ext_overflowed": [int(prof["to_tier2"]), int(prof["to_tier3"]),
-                                   int(prof["to_tier4"]), int(prof["to_band"])]}
+                                   int(prof["to_tier4"]), int(prof["to_tier5"]),
+                                   int(prof["to_band"])]}
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.int32, device=dev)  # 1 GiB

@@ -130,8 +130,8 @@ typedef struct {
   int32_t x_tier1;      /* tasks with X <= x_tier1 start in the 64-cell window (default 32) */
   int32_t x_tier2;      /* X <= x_tier2 start in the 128-cell window (default 80); larger X
                            start in the 256-cell window.  An extension whose band outgrows its
-                           window is re-run in the next wider one (64, 128, 256, 1024), and
-                           past 1024 cells in the band tier (band kept in device memory). */
+                           window is re-run in the next wider one (64, 128, 256, 512, 1024),
+                           and past 1024 cells in the band tier (band kept in device memory). */
   int32_t band_blocks;  /* workgroups of the band tier, 0..1024; each holds 12 * (longest read
                            of the store + 64) bytes or so of scratch.  0 = as many as fit in
                            64 MiB, at most 16 */
@@ -249,11 +249,12 @@ typedef struct {
   uint64_t extensions;    /* extensions started in the 64-cell tier (2 per task) */
   uint64_t to_tier2;      /* extensions moved from the 64- to the 128-cell window */
   uint64_t to_tier3;      /* moved from the 128- to the 256-cell window */
-  uint64_t to_tier4;      /* moved from the 256- to the 1024-cell window */
+  uint64_t to_tier4;      /* moved from the 256- to the 512-cell window */
+  uint64_t to_tier5;      /* moved from the 512- to the 1024-cell window */
   uint64_t to_band;       /* moved from the 1024-cell window to the band tier */
   double ms_tier1;        /* summed time of the 64-cell tier (and, in the batched form,
                              the queue build before it) */
-  double ms_wide;         /* summed time of the 128-, 256- and 1024-cell and band tiers */
+  double ms_wide;         /* summed time of the wider windows and the band tier */
   double ms_combine;      /* summed time of the combine kernel */
   double ms_total;        /* first to last event, summed over calls */
 } xd_profile;

@@ -54,7 +54,8 @@ class ServerCounters(ctypes.Structure):
 class Profile(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_uint64), ("extensions", ctypes.c_uint64),
                 ("to_tier2", ctypes.c_uint64), ("to_tier3", ctypes.c_uint64),
-                ("to_tier4", ctypes.c_uint64), ("to_band", ctypes.c_uint64),
+                ("to_tier4", ctypes.c_uint64), ("to_tier5", ctypes.c_uint64),
+                ("to_band", ctypes.c_uint64),
                 ("ms_tier1", ctypes.c_double), ("ms_wide", ctypes.c_double),
                 ("ms_combine", ctypes.c_double), ("ms_total", ctypes.c_double)]
 

@@ -1,10 +1,10 @@
 // libxdrop: C ABI for X-drop seed-and-extend on MI355X (declared in
 // include/xdrop.h), with the batch kernels it launches.
 //
-// Windows ("tiers") of 64, 128, 256 and 1024 cells; an extension whose band
-// outgrows its window is appended to the next tier's overflow list and re-run
-// there from the start.  Past 1024 cells the band tier keeps the band in
-// global memory (one workgroup per extension), so no result is truncated.
+// Windows ("tiers") of 64, 128, 256, 512 and 1024 cells; an extension whose
+// band outgrows its window is appended to the next tier's overflow list and
+// re-run there from the start.  Past 1024 cells the band tier keeps the band
+// in global memory (one workgroup per extension), so no result is truncated.
 //
 // Plain form (xd_align_batch), stream-ordered on the caller's stream:
 //   k_reset      zero the counters and the histogram
@@ -94,27 +94,27 @@ uint64_t band_bytes(const BandGeom& b) { return (uint64_t)b.blocks * 12ull * (ui
 struct Scratch {
   ExtOut* ext;        // [2n]
   uint32_t* queue;    // [2n] extension ids: tier-major, longest first
-  uint32_t* ovf[4];   // [2n] each: overflow of tier t into tier t+1 (3: band)
+  uint32_t* ovf[5];   // [2n] each: overflow of tier t into tier t+1 (4: band)
   uint32_t* hist;     // [kBins] histogram, then running cursors
   uint32_t* ctr;      // [32] counters, see below
-  void* targs;        // [5] TierArgs of the four windows and the band tier
+  void* targs;        // [6] TierArgs of the five windows and the band tier
   int32_t* band;      // [blocks][3][cap] rows of the band tier
   BandGeom geom;
 };
 // ctr layout
-constexpr int kOvfCount = 0;   // [0..3] sizes of ovf[0..3]
-constexpr int kHead = 4;       // [4..7] work heads of tiers 0..3
-constexpr int kSeg = 8;        // [8..12] queue start of tiers 0..3, then 2n
-constexpr int kBandHead = 13;  // work head of the band tier
+constexpr int kOvfCount = 0;   // [0..4] sizes of ovf[0..4]
+constexpr int kHead = 5;       // [5..9] work heads of tiers 0..4
+constexpr int kSeg = 10;       // [10..14] queue start of segments 0..3, then 2n
+constexpr int kBandHead = 15;  // work head of the band tier
 constexpr int kCtrWords = 32;
-constexpr int kTierArgsBytes = 5 * 256;  // >= 5 * sizeof(TierArgs), checked below
+constexpr int kTierArgsBytes = 6 * 256;  // >= 6 * sizeof(TierArgs), checked below
 constexpr uint64_t kFixedBytes = (kBins * 4 + kCtrWords * 4 + kTierArgsBytes + 255) & ~255ull;
 
 uint64_t scratch_bytes(uint64_t n, const BandGeom& g) {
   const uint64_t n_ext = 2 * n;
   const uint64_t ext = (n_ext * sizeof(ExtOut) + 255) & ~255ull;
   const uint64_t list = (n_ext * 4 + 255) & ~255ull;
-  return ext + 5 * list + kFixedBytes + band_bytes(g);
+  return ext + 6 * list + kFixedBytes + band_bytes(g);
 }
 
 Scratch scratch_carve(char* base, uint64_t n, const BandGeom& g) {
@@ -124,8 +124,8 @@ Scratch scratch_carve(char* base, uint64_t n, const BandGeom& g) {
   Scratch s;
   s.ext = (ExtOut*)base;
   s.queue = (uint32_t*)(base + ext);
-  for (int q = 0; q < 4; ++q) s.ovf[q] = (uint32_t*)(base + ext + (1 + q) * list);
-  char* fixed = base + ext + 5 * list;
+  for (int q = 0; q < 5; ++q) s.ovf[q] = (uint32_t*)(base + ext + (1 + q) * list);
+  char* fixed = base + ext + 6 * list;
   s.hist = (uint32_t*)fixed;
   s.ctr = (uint32_t*)(fixed + kBins * 4);
   s.targs = fixed + kBins * 4 + kCtrWords * 4;
@@ -146,11 +146,11 @@ struct TierArgs {
   uint32_t* out_count;
 };
 
-static_assert(5 * sizeof(TierArgs) <= kTierArgsBytes, "tier argument area");
+static_assert(6 * sizeof(TierArgs) <= kTierArgsBytes, "tier argument area");
 static_assert(sizeof(TierArgs) % 4 == 0, "tier arguments copied by words");
 
 struct TierPack {
-  TierArgs t[5];
+  TierArgs t[6];
 };
 
 // ---- per-task validation (shared by the extension and combine kernels) ----
@@ -362,8 +362,8 @@ __global__ __launch_bounds__(256) void k_bin_hist(BatchArgs A, BinRule R, uint32
 }
 
 // hist[b] <- number of extensions with a smaller key (queue start of key b);
-// seg[t] <- queue start of tier t (seg[3] also covers the invalid tasks),
-// seg[4] = n_ext
+// seg[t] <- queue start of segment t (segments 0..2: first tiers from X;
+// segment 3: invalid tasks), seg[4] = n_ext
 __global__ __launch_bounds__(256) void k_bin_scan(uint32_t* hist, uint32_t* seg,
                                                   uint32_t n_ext) {
   __shared__ uint32_t h[kBins];
@@ -435,10 +435,11 @@ int device_cus() {
   return cus;
 }
 
-// tiers 1..3 (128, 256, 1024 cells): queue segments (batched form only) and
-// overflow lists of the tier below
-// tier arguments: tier 0 (64 cells, batched form) and tiers 1..3 (128, 256,
-// 1024 cells) with their queue segments (batched form) and overflow lists
+// tier arguments: tier 0 (64 cells, batched form), tiers 1..4 (128, 256, 512,
+// 1024 cells) and the band tier, each with its queue segment (batched form;
+// segments 0..2 hold the extensions whose X picks that first tier, segment 3
+// the invalid tasks, which tier 3 marks) and the overflow list of the tier
+// below
 TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
   uint32_t* c = S.ctr;
   TierPack p;
@@ -450,7 +451,9 @@ TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
             c + kHead + 2, S.ovf[2], c + kOvfCount + 2};
   p.t[3] = {A, S.queue, segs ? c + kSeg + 3 : nullptr, S.ovf[2], c + kOvfCount + 2,
             c + kHead + 3, S.ovf[3], c + kOvfCount + 3};
-  p.t[4] = {A, S.queue, nullptr, S.ovf[3], c + kOvfCount + 3, c + kBandHead, nullptr, nullptr};
+  p.t[4] = {A, S.queue, nullptr, S.ovf[3], c + kOvfCount + 3, c + kHead + 4, S.ovf[4],
+            c + kOvfCount + 4};
+  p.t[5] = {A, S.queue, nullptr, S.ovf[4], c + kOvfCount + 4, c + kBandHead, nullptr, nullptr};
   return p;
 }
 
@@ -459,9 +462,11 @@ void launch_wide(const Scratch& S, uint32_t blocks, hipStream_t stream) {
   const TierArgs* ta = (const TierArgs*)S.targs;
   hipLaunchKernelGGL((k_ext_tier<2, 8, UNIT, 4>), dim3(blocks), dim3(256), 0, stream, ta + 1);
   hipLaunchKernelGGL((k_ext_tier<4, 4, UNIT, 4>), dim3(blocks), dim3(256), 0, stream, ta + 2);
-  hipLaunchKernelGGL((k_ext_tier<16, 2, UNIT, 1>), dim3(4 * blocks), dim3(64), 0, stream,
+  hipLaunchKernelGGL((k_ext_tier<8, 4, UNIT, 2>), dim3(2 * blocks), dim3(128), 0, stream,
                      ta + 3);
-  hipLaunchKernelGGL(k_ext_band, dim3(S.geom.blocks), dim3(64 * kBandWaves), 0, stream, ta + 4,
+  hipLaunchKernelGGL((k_ext_tier<16, 2, UNIT, 1>), dim3(4 * blocks), dim3(64), 0, stream,
+                     ta + 4);
+  hipLaunchKernelGGL(k_ext_band, dim3(S.geom.blocks), dim3(64 * kBandWaves), 0, stream, ta + 5,
                      S.band, S.geom.cap);
 }
 
@@ -937,7 +942,8 @@ int xd_profile_read(xd_profile* out, int reset) {
     g_prof_sum.to_tier2 += r.counters[kOvfCount + 0];
     g_prof_sum.to_tier3 += r.counters[kOvfCount + 1];
     g_prof_sum.to_tier4 += r.counters[kOvfCount + 2];
-    g_prof_sum.to_band += r.counters[kOvfCount + 3];
+    g_prof_sum.to_tier5 += r.counters[kOvfCount + 3];
+    g_prof_sum.to_band += r.counters[kOvfCount + 4];
     g_prof_sum.ms_tier1 += t1;
     g_prof_sum.ms_wide += t2;
     g_prof_sum.ms_combine += t3;

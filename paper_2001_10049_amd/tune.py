@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned.json")
 
 SPACE = {
-    "waves_per_cu": (16, 24, 32),
+    "waves_per_cu": (16, 24, 28, 32),
     "group_steps": (8, 16),
     "x_tier1": (24, 32, 40),
     "x_tier2": (64, 80, 112),
@@ -90,7 +90,7 @@ def time_tuning(store, pairs, seeds, x, k, tuning, reps=3):
     return best
 
 
-def autotune(w, slice_tasks=20000, seed=0, log=print):
+def autotune(w, slice_tasks=100000, seed=0, log=print):
     """Sweeps the tuning space on a slice of w; returns (best, table)."""
     import paper_2001_10049_amd as xd
     rng = np.random.default_rng(seed)
@@ -111,7 +111,7 @@ def autotune(w, slice_tasks=20000, seed=0, log=print):
 def main():
     ap = argparse.ArgumentParser(description="autotune the batched form")
     ap.add_argument("--workload", nargs="+", default=["c2", "c3"])
-    ap.add_argument("--slice", type=int, default=20000)
+    ap.add_argument("--slice", type=int, default=100000)
     ap.add_argument("--out", default=CACHE, help="where to write the merged cache")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))

@@ -17,10 +17,14 @@
 // distribution classes.
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <random>
+#include <thread>
 #include <vector>
 
 namespace {
@@ -351,6 +355,8 @@ void make_coverage_reads(Rng& R, const Params& P, Dataset& D) {
   const uint64_t G = D.genome.size();
   const double want = P.depth * (double)G;
   double have = 0;
+  const bool big = P.genome_len >= 20000000;
+  double next_report = 5e8;
   while (have < want) {
     uint32_t L = draw_len(R, P);
     uint64_t span = (uint64_t)(L * 1.25) + 64;
@@ -360,6 +366,10 @@ void make_coverage_reads(Rng& R, const Params& P, Dataset& D) {
     if (!make_read(R, P, D, ts, L, P.len_min, r)) continue;
     have += r.len;
     D.reads.push_back(std::move(r));
+    if (big && have >= next_report) {
+      fprintf(stderr, "synth: %.1f of %.1f Gbp of reads\n", have * 1e-9, want * 1e-9);
+      next_report += 5e8;
+    }
   }
 }
 
@@ -388,25 +398,56 @@ void make_coverage_tasks(Rng& R, const Params& P, Dataset& D) {
   for (uint32_t i = 0; i < nr; ++i) order[i] = i;
   std::sort(order.begin(), order.end(),
             [&](uint32_t x, uint32_t y) { return D.reads[x].ts < D.reads[y].ts; });
-  // candidate pairs: template overlap >= min_overlap and >= 1 true seed
+  // candidate pairs: template overlap >= min_overlap and >= 1 true seed.
+  // Reads are scanned in chunks on several threads; the chunks' pairs are
+  // concatenated in chunk order, so the list is the same as a serial scan.
+  const bool spaced = P.seeds_per_pair != 0;
+  const uint32_t kChunk = 2048;
+  const uint32_t n_chunks = (nr + kChunk - 1) / kChunk;
+  std::vector<std::vector<PairRef>> cp(n_chunks);
+  std::vector<std::vector<uint32_t>> cn(n_chunks);
+  std::atomic<uint32_t> next{0};
+  auto worker = [&]() {
+    std::vector<uint64_t> tmp;
+    for (;;) {
+      const uint32_t c = next.fetch_add(1);
+      if (c >= n_chunks) break;
+      const uint32_t x1 = std::min(nr, (c + 1) * kChunk);
+      for (uint32_t x = c * kChunk; x < x1; ++x) {
+        const Read& A = D.reads[order[x]];
+        for (uint32_t y = x + 1; y < nr; ++y) {
+          const Read& B = D.reads[order[y]];
+          if (B.ts + P.min_overlap > A.te) break;
+          uint64_t ohi = std::min(A.te, B.te);
+          if (ohi < B.ts + P.min_overlap) continue;
+          pair_seeds(D, P, order[x], order[y], spaced, tmp);
+          if (tmp.empty()) continue;
+          cp[c].push_back({order[x], order[y]});
+          cn[c].push_back((uint32_t)tmp.size());
+        }
+      }
+    }
+  };
+  unsigned n_threads = std::thread::hardware_concurrency();
+  if (const char* e = getenv("OMP_NUM_THREADS")) n_threads = (unsigned)atoi(e);
+  n_threads = std::max(1u, std::min(n_threads, 64u));
+  std::vector<std::thread> pool;
+  for (unsigned q = 1; q < n_threads; ++q) pool.emplace_back(worker);
+  worker();
+  for (auto& t : pool) t.join();
   std::vector<PairRef> pairs;
   std::vector<uint32_t> nseed;  // per pair: seeds (spaced if seeds_per_pair)
-  std::vector<uint64_t> tmp;
-  const bool spaced = P.seeds_per_pair != 0;
-  for (uint32_t x = 0; x < nr; ++x) {
-    const Read& A = D.reads[order[x]];
-    for (uint32_t y = x + 1; y < nr; ++y) {
-      const Read& B = D.reads[order[y]];
-      if (B.ts + P.min_overlap > A.te) break;
-      uint64_t ohi = std::min(A.te, B.te);
-      if (ohi < B.ts + P.min_overlap) continue;
-      pair_seeds(D, P, order[x], order[y], spaced, tmp);
-      if (tmp.empty()) continue;
-      pairs.push_back({order[x], order[y]});
-      nseed.push_back((uint32_t)tmp.size());
-    }
+  for (uint32_t c = 0; c < n_chunks; ++c) {
+    pairs.insert(pairs.end(), cp[c].begin(), cp[c].end());
+    nseed.insert(nseed.end(), cn[c].begin(), cn[c].end());
+    std::vector<PairRef>().swap(cp[c]);
+    std::vector<uint32_t>().swap(cn[c]);
   }
+  std::vector<uint64_t> tmp;
   D.n_candidate_pairs = pairs.size();
+  if (P.genome_len >= 20000000)
+    fprintf(stderr, "synth: %llu candidate pairs from %u reads\n",
+            (unsigned long long)pairs.size(), nr);
   uint64_t n_true = P.n_tasks;
   uint64_t n_spur = 0;
   if (P.spurious_frac > 0 && !D.copy_pos.empty()) {
@@ -514,12 +555,15 @@ typedef Params synth_params;
 void* synth_make(const synth_params* P) {
   Dataset* D = new Dataset();
   Rng R(P->seed);
+  const bool big = P->genome_len >= 20000000;  // report phases of the large recipes
   build_genome(R, *P, *D);
   if (P->mode == 0) {
     make_pairs_mode(R, *P, *D);
   } else {
     make_coverage_reads(R, *P, *D);
+    if (big) fprintf(stderr, "synth: %zu reads\n", D->reads.size());
     if (P->n_tasks > 0) make_coverage_tasks(R, *P, *D);
+    if (big) fprintf(stderr, "synth: %zu tasks\n", D->ra.size());
   }
   return D;
 }
