@@ -378,12 +378,34 @@ __global__ __launch_bounds__(256) void k_bin_scan(uint32_t* hist, uint32_t* seg,
   if (threadIdx.x == 0) seg[4] = n_ext;
 }
 
+// Each block places kScatterItems extensions: it counts its keys in LDS,
+// claims one range per key from the global cursors (one atomic per key it
+// holds, not per extension), then writes each extension into its range.
+constexpr uint32_t kScatterPerThread = 4;
+constexpr uint32_t kScatterItems = 256 * kScatterPerThread;
+
 __global__ __launch_bounds__(256) void k_bin_scatter(BatchArgs A, BinRule R, uint32_t n_ext,
                                                      uint32_t* cursor, uint32_t* queue) {
-  const uint32_t e = blockIdx.x * 256u + threadIdx.x;
-  if (e >= n_ext) return;
-  const uint32_t pos = atomicAdd(&cursor[ext_key(A, R, e)], 1u);
-  queue[pos] = e;
+  __shared__ uint32_t cnt[kBins];
+  for (int b = threadIdx.x; b < kBins; b += 256) cnt[b] = 0;
+  __syncthreads();
+  const uint32_t first = blockIdx.x * kScatterItems + threadIdx.x;
+  uint32_t key[kScatterPerThread], rank[kScatterPerThread];
+#pragma unroll
+  for (uint32_t q = 0; q < kScatterPerThread; ++q) {
+    const uint32_t e = first + 256u * q;
+    key[q] = e < n_ext ? ext_key(A, R, e) : 0u;
+    rank[q] = e < n_ext ? atomicAdd(&cnt[key[q]], 1u) : 0u;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kBins; b += 256)
+    if (cnt[b]) cnt[b] = atomicAdd(&cursor[b], cnt[b]);  // now: the block's start in bin b
+  __syncthreads();
+#pragma unroll
+  for (uint32_t q = 0; q < kScatterPerThread; ++q) {
+    const uint32_t e = first + 256u * q;
+    if (e < n_ext) queue[cnt[key[q]] + rank[q]] = e;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_combine(BatchArgs A) {
@@ -495,8 +517,8 @@ void launch_persistent_ext(const BatchArgs& A, const Scratch& S, uint64_t n_ext,
                      S.hist);
   hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(256), 0, stream, S.hist, S.ctr + kSeg,
                      (uint32_t)n_ext);
-  hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(256), 0, stream, A, R, (uint32_t)n_ext,
-                     S.hist, S.queue);
+  hipLaunchKernelGGL(k_bin_scatter, dim3((uint32_t)((n_ext + kScatterItems - 1) / kScatterItems)),
+                     dim3(256), 0, stream, A, R, (uint32_t)n_ext, S.hist, S.queue);
   uint32_t blocks = (uint32_t)device_cus() * (uint32_t)tu.waves_per_cu / 4u;
   if (blocks < 1) blocks = 1;
   if (tu.group_steps == 4)
