@@ -189,17 +189,22 @@ __device__ __forceinline__ int32_t sctz64(uint64_t v) {
   return r;
 }
 
-// imp[K] for the largest K <= T with imp[K] != 0 (K + 1 in kk), or kk = 0;
-// tested from the last step down, so the scan stops at the first hit
-template <int T, int G>
-__device__ __forceinline__ void last_nonzero(const uint64_t (&imp)[G], uint64_t& mask,
-                                             int32_t& kk) {
+// The slot masks imp[K][*] of the largest K <= T where any is nonzero
+// (K + 1 in kk), or kk = 0; tested from the last step down, so the scan
+// stops at the first hit
+template <int T, int G, int CPL>
+__device__ __forceinline__ void last_nonzero(const uint64_t (&imp)[G][CPL],
+                                             uint64_t (&mask)[CPL], int32_t& kk) {
   if constexpr (T >= 0) {
-    if (imp[T]) {
-      mask = imp[T];
+    uint64_t a = imp[T][0];
+#pragma unroll
+    for (int c = 1; c < CPL; ++c) a |= imp[T][c];
+    if (a) {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) mask[c] = imp[T][c];
       kk = T + 1;
     } else {
-      last_nonzero<T - 1, G>(imp, mask, kk);
+      last_nonzero<T - 1, G, CPL>(imp, mask, kk);
     }
   }
 }
@@ -395,53 +400,84 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
     d += G;
   };
 
-  // A full group clear of the walls, for match == 1 and one cell per lane
-  // (the 64-cell window).  Inside the grid a cell is evaluated iff its left,
-  // up or diagonal predecessor is live, so antidiagonal d+1's evaluated
-  // lanes are also L_d | (L_d | L_{d-1}) << 1 from the live masks, added to
-  // the lane counts with the mask as carry-in: one vector instruction and
-  // three scalar ones instead of two vector ones.  Every other step counts
-  // that way, which balances the vector and scalar issue rates.  Each
-  // step's improving mask stays in a scalar register; the arg-max is taken
-  // once after the group from the last step that improved (T rose by 1 on
-  // exactly those steps).
-  auto group_unit1 = [&](auto len_tag) {
+  // A group clear of the walls for match == 1 in the 64- and 128-cell
+  // windows.  Inside the grid a cell is evaluated iff its left, up or
+  // diagonal predecessor is live, so antidiagonal d+1's evaluated cells are
+  // read off the live masks of d and d-1 (slot c's up and diagonal
+  // neighbours are slot c-1 of the same lane, or for slot 0 the last slot of
+  // the lane below, one bit down) and added to the lane counts with the mask
+  // as carry-in: one vector instruction and two or three scalar ones per slot
+  // instead of two vector ones.  Every other step counts that way, which
+  // balanced the vector and scalar issue rates best of the splits measured.
+  // Each step's improving masks stay in scalar registers; the arg-max is
+  // taken once after the group from the last step that improved (T rose by
+  // 1 on exactly those steps).
+  auto group_unit = [&](auto len_tag) {
     constexpr int G = decltype(len_tag)::value;
-    const int32_t r = (d + 1 - base - lane) & MASK;
+    const int32_t r = (d + 1 - base - irow - (CPL - 1)) & MASK;
     const uint8_t* rbytes = (const uint8_t*)ring;
-    const uint32_t ad = ((uint32_t)r << 2) + aa[0];
-    uint32_t bmv[G];
+    uint32_t bmv[G][CPL];
 #pragma unroll
-    for (int t = 0; t < G; ++t) bmv[t] = rbytes[ad + 4 * t];
-    uint64_t imp[G];
-    uint64_t Ld = Lc[0], Lm = Lp[0];
+    for (int c = 0; c < CPL; ++c) {
+      const uint32_t ad = ((uint32_t)(r + (CPL - 1 - c)) << 2) + aa[c];
+#pragma unroll
+      for (int t = 0; t < G; ++t) bmv[t][c] = rbytes[ad + 4 * t];
+    }
+    uint64_t imp[G][CPL];
+    uint64_t Ld[CPL], Lm[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      Ld[c] = Lc[c];
+      Lm[c] = Lp[c];
+    }
     const int32_t thr0 = thr;
     auto body = [&](auto t_tag) {
       constexpr int t = decltype(t_tag)::value;
+      constexpr bool by_masks = (t & 1) == 0;
       const int32_t timp = thr + X;
-      const int32_t upv = shr1_zero(U1[0]);
-      const int32_t s = max(max(Up[0] + (int32_t)bmv[t] + C, upv), U1[0]);
-      if constexpr ((t & 1) == 0)
-        cnt = add_lane_bit(cnt, Ld | ((Ld | Lm) << 1));
-      else
-        cnt += (s > kEvMin) ? 1u : 0u;
-      const bool lv = s >= thr;
-      const uint64_t L = ballot64(lv);
-      imp[t] = ballot64(s > timp);
-      Up[0] = upv;
-      U1[0] = lv ? s : 0;
-      thr = add_nonzero(thr, g, imp[t]);
-      Lm = Ld;
-      Ld = L;
+      int32_t upv[CPL];
+      upv[0] = shr1_zero(U1[CPL - 1]);
+#pragma unroll
+      for (int c = 1; c < CPL; ++c) upv[c] = U1[c - 1];
+      if constexpr (by_masks) {
+        cnt = add_lane_bit(cnt, Ld[0] | ((Ld[CPL - 1] | Lm[CPL - 1]) << 1));
+#pragma unroll
+        for (int c = 1; c < CPL; ++c) cnt = add_lane_bit(cnt, Ld[c] | Ld[c - 1] | Lm[c - 1]);
+      }
+      uint64_t any = 0, L[CPL];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int32_t sv = max(max(Up[c] + (int32_t)bmv[t][c] + C, upv[c]), U1[c]);
+        if constexpr (!by_masks) cnt += (sv > kEvMin) ? 1u : 0u;
+        const bool lv = sv >= thr;
+        L[c] = ballot64(lv);
+        imp[t][c] = ballot64(sv > timp);
+        any |= imp[t][c];
+        Up[c] = upv[c];
+        U1[c] = lv ? sv : 0;
+      }
+      thr = add_nonzero(thr, g, any);
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        Lm[c] = Ld[c];
+        Ld[c] = L[c];
+      }
     };
     static_for<G>(body);
-    Lc[0] = Ld;
-    Lp[0] = Lm;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      Lc[c] = Ld[c];
+      Lp[c] = Lm[c];
+    }
     if (thr != thr0 + G * g) {
-      uint64_t lm = 0;
+      uint64_t lm[CPL];
       int32_t kk = 0;
-      last_nonzero<G - 1, G>(imp, lm, kk);
-      bi = base + sctz64(lm);
+      last_nonzero<G - 1, G, CPL>(imp, lm, kk);
+      int32_t cell = 0x7fffffff;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c)
+        if (lm[c]) cell = min(cell, sctz64(lm[c]) * CPL + c);
+      bi = base + cell;
       dstar = d + kk;
     }
     d += G;
@@ -461,7 +497,7 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
       const int32_t c = (z - GS) | (z + (m - base - 63 - GS)) | (lo - dv + (n - GS)) |
                         (filled - dv - GS);
       if (c >= 0) {
-        group_unit1(std::integral_constant<int, GS>{});
+        group_unit(std::integral_constant<int, GS>{});
         continue;
       }
       // the two usual reasons it fails, handled here and tested again: the
@@ -478,6 +514,47 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
           Lc[0] >>= lo;
           Lp[0] >>= lo;
           base += lo;
+          load_a();
+          continue;
+        }
+        if (filled < dv + GS) {
+          fill_to(d + GS - base);
+          continue;
+        }
+      }
+    } else if constexpr (UNIT && CPL == 2) {
+      // the same for two cells per lane, with the band's rows taken slot by slot
+      int32_t hi = -1, lo = Q;
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) {
+        const uint64_t M = Lc[k] | Lp[k];
+        const int32_t h = (63 - sclz64(M)) * CPL + k;
+        const int32_t l = sctz64(M) * CPL + k;
+        hi = M ? max(hi, h) : hi;
+        lo = M ? min(lo, l) : lo;
+      }
+      const int32_t dv = d - base;
+      const int32_t c = hi | (Q - 1 - GS - hi) | (m - base - hi - GS) | (lo - dv + (n - GS)) |
+                        (filled - dv - GS);
+      if (c >= 0) {
+        group_unit(std::integral_constant<int, GS>{});
+        continue;
+      }
+      if (hi >= 0 && (m + n - 1 - d) >= 0) {
+        const int32_t sl = lo / CPL;
+        if (hi + GS > Q - 1 && sl > 0) {
+          const int src = lane + sl;
+          const bool inside = src < 64;
+#pragma unroll
+          for (int k = 0; k < CPL; ++k) {
+            const int32_t u1 = __builtin_amdgcn_ds_bpermute((src & 63) << 2, U1[k]);
+            const int32_t up = __builtin_amdgcn_ds_bpermute((src & 63) << 2, Up[k]);
+            U1[k] = inside ? u1 : 0;
+            Up[k] = inside ? up : 0;
+            Lc[k] >>= sl;
+            Lp[k] >>= sl;
+          }
+          base += sl * CPL;
           load_a();
           continue;
         }
@@ -531,8 +608,8 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
     if (full) {
       const bool fast = ((room_a - GS) | (room_b - GS)) >= 0;
       if (fast) {
-        if constexpr (UNIT && CPL == 1)
-          group_unit1(std::integral_constant<int, GS>{});
+        if constexpr (UNIT && CPL <= 2)
+          group_unit(std::integral_constant<int, GS>{});
         else
           group(std::false_type{}, std::integral_constant<int, GS>{});
       } else {
@@ -541,8 +618,8 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
     } else {
       const bool fast = ((room_a - kShort) | (room_b - kShort)) >= 0;
       if (fast) {
-        if constexpr (UNIT && CPL == 1)
-          group_unit1(std::integral_constant<int, kShort>{});
+        if constexpr (UNIT && CPL <= 2)
+          group_unit(std::integral_constant<int, kShort>{});
         else
           group(std::false_type{}, std::integral_constant<int, kShort>{});
       } else {

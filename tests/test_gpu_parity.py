@@ -287,3 +287,45 @@ def test_plan_replays_and_input_rewrites():
         del junk
     plan.close()
     store.close()
+
+
+def random_flank_workload(n_pairs=300, length=6000, seed=21):
+    """Unrelated read pairs sharing one planted 17-mer: every extension runs
+    into random sequence, where X = 25 bands widen to 100-400 cells."""
+    rng = np.random.default_rng(seed)
+    reads, tasks = [], []
+    for p in range(n_pairs):
+        a, b = rand_codes(rng, length), rand_codes(rng, length)
+        pa, pb = int(rng.integers(0, length - 17)), int(rng.integers(0, length - 17))
+        b[pb:pb + 17] = a[pa:pa + 17]
+        reads += [a, b]
+        tasks.append((2 * p, 2 * p + 1, pa, pb, (25, 50)[p % 2]))
+    return workload_from(reads, tasks)
+
+
+@pytest.mark.parametrize("form", ["plain", "persistent", "plan"])
+def test_wide_windows_parity(form):
+    # the 128-, 256- and 512-cell windows, reached by overflow
+    w = random_flank_workload()
+    print("wide windows", form, flush=True)
+    ref = oracle.align_workload(w)
+    xd.profile_enable(True)
+    xd.profile_read(reset=True)
+    store = xd.ReadStore.from_workload(w)
+    pairs, seeds, xs = xd.workload_tensors(w, "cuda")
+    if form == "plan":
+        plan = xd.Plan(store, pairs, seeds, x=xs, k=w.k)
+        out = plan.launch()
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        plan.close()
+    else:
+        out = xd.align_batch(store, pairs, seeds, x=xs, k=w.k, persistent=form == "persistent")
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+    prof = xd.profile_read(reset=True)
+    xd.profile_enable(False)
+    store.close()
+    assert_same(got, ref, label="wide " + form)
+    if form != "plan":
+        assert prof["to_tier3"] > 0 and prof["to_tier4"] > 0, prof
