@@ -61,6 +61,7 @@ extern "C" {
 #define XD_TASK_BAD_X 3    /* X < 0 or X > XD_X_MAX */
 #define XD_TASK_BAND_OVERFLOW 4 /* reserved: no longer produced (bands wider than the
                                    1024-cell window run in the band tier) */
+#define XD_TASK_NO_SEED 5  /* xd_align_pairs: the pair's seed list is empty */
 
 /* limits (checked; violations return XD_EINVAL) */
 #define XD_X_MAX (1 << 20)           /* largest X */
@@ -147,6 +148,51 @@ int xd_align_batch_persistent(const xd_store* store, const uint32_t* pairs,
                               int32_t gap, int32_t* score, uint32_t* beg, uint32_t* end,
                               int32_t* status, uint64_t* cells, const xd_tuning* tuning,
                               void* hip_stream);
+
+/* ---- multi-seed pairs and strands ----------------------------------------- */
+
+/* Aligns n_pairs candidate pairs, each from several seeds, and keeps each
+ * pair's best (the paper's seed exploration: section 5 runs one seed per
+ * pair, all seeds at least the k-mer length apart, or seeds 1,000 bp apart;
+ * section 8 names a minimum distance between seeds and a maximum number of
+ * seeds per overlap as the parameters).
+ *
+ * Device pointers, caller-owned:
+ *   pairs    uint32[2 n_pairs]   (A, B) read ids
+ *   rc       uint8[n_pairs]      nonzero: the reads overlap on opposite strands
+ *                                and B is aligned reverse-complemented, i.e.
+ *                                against B' = complement of B read backwards;
+ *                                seed positions and result coordinates for B
+ *                                are then positions in B'.  NULL: all forward
+ *   seed_off uint64[n_pairs+1]   pair p's seeds are entries [seed_off[p],
+ *                                seed_off[p+1]) of seeds; n_seeds (host value)
+ *                                must equal seed_off[n_pairs]
+ *   seeds    uint32[2 n_seeds]   (pa, pb) k-mer starts, in the order the
+ *                                selection scans them (normally increasing pa)
+ *   x        int32[n_pairs]      X per pair, or NULL to use x_scalar
+ * Selection: scanning a pair's list in order, a seed is kept when it is the
+ * first kept one or its pa is at least min_dist past the last kept seed's pa,
+ * until max_seeds are kept (0 = no limit).  min_dist = k is the all-seed
+ * option, 1000 the 1 kbp one, max_seeds = 1 the one-seed one.  Each kept seed
+ * is aligned exactly as an xd_align_batch task (same score, coordinates and
+ * cells).  Per pair outputs:
+ *   score, beg[2], end[2]  of the best kept seed by score (the earliest kept
+ *                          one on equal scores); INT32_MIN and 0 without one
+ *   status    XD_TASK_OK when a kept seed aligned; otherwise the first kept
+ *             seed's status, XD_TASK_NO_SEED for an empty list, or
+ *             XD_TASK_BAD_SEED when the pair's range is not inside [0, n_seeds]
+ *   seed_idx  the best seed's index in the pair's list (0xffffffff without)
+ *   n_kept    seeds kept;  cells  evaluated cells summed over the kept seeds
+ * Runs the batched form on the kept seeds (tuning as for
+ * xd_align_batch_persistent) on hip_stream, asynchronously, with
+ * stream-ordered scratch of about 140 bytes per listed seed. */
+int xd_align_pairs(const xd_store* store, uint64_t n_pairs, const uint32_t* pairs,
+                   const uint8_t* rc, const uint64_t* seed_off, const uint32_t* seeds,
+                   uint64_t n_seeds, const int32_t* x, int32_t x_scalar, int32_t min_dist,
+                   int32_t max_seeds, int32_t k, int32_t match, int32_t mismatch, int32_t gap,
+                   int32_t* score, uint32_t* beg, uint32_t* end, int32_t* status,
+                   uint32_t* seed_idx, uint32_t* n_kept, uint64_t* cells,
+                   const xd_tuning* tuning, void* hip_stream);
 
 /* A captured batch: the batched form's kernels recorded once in a hipGraph
  * for fixed buffers (same meaning as xd_align_batch's) and replayed by

@@ -13,7 +13,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (READ_MAX, SCORE_LIMIT, TASK_BAD_READ, TASK_BAD_SEED, TASK_BAD_X,  # noqa
-                   TASK_BAND_OVERFLOW, TASK_OK, X_MAX, XdropError)
+                   TASK_BAND_OVERFLOW, TASK_NO_SEED, TASK_OK, X_MAX, XdropError)
 
 
 def _p(a) -> ctypes.c_void_p:
@@ -163,6 +163,47 @@ def align_batch(store: ReadStore, pairs, seeds, x=None, x_scalar=0, k=17, match=
         _lib.check(lib.xd_align_batch_persistent(*args, _tuning(tuning), _stream_ptr(stream)))
     else:
         _lib.check(lib.xd_align_batch(*args, _stream_ptr(stream)))
+    return out
+
+
+def align_pairs(store: ReadStore, pairs, seed_off, seeds, rc=None, x=None, x_scalar=0,
+                min_dist=17, max_seeds=0, k=17, match=1, mismatch=-1, gap=-1, n_seeds=None,
+                stream=None, tuning=None):
+    """Multi-seed pair alignment (xd_align_pairs): per pair, choose seeds from
+    its list, align each, keep the best.
+
+    pairs: [n, 2] 4-byte device tensor; seed_off: int64 [n + 1]; seeds:
+    [S, 2] 4-byte; rc: uint8 [n] or None; x: int32 [n] or None.  n_seeds
+    defaults to seed_off[-1] (read back from the device).  Returns dict of
+    device tensors per pair: score, beg, end, status, seed_idx, n_kept, cells.
+    """
+    import torch
+    n = int(pairs.shape[0])
+    dev = pairs.device
+    _check_dev("pairs", pairs, 2 * n, 4)
+    _check_dev("seed_off", seed_off, n + 1, 8)
+    if n_seeds is None:
+        n_seeds = int(seed_off[-1].item()) if n else 0
+    if n_seeds:
+        _check_dev("seeds", seeds, 2 * n_seeds, 4)
+    if rc is not None:
+        _check_dev("rc", rc, n, 1)
+    if x is not None:
+        _check_dev("x", x, n, 4)
+    out = dict(score=torch.empty(n, dtype=torch.int32, device=dev),
+               beg=torch.empty((n, 2), dtype=torch.int32, device=dev),
+               end=torch.empty((n, 2), dtype=torch.int32, device=dev),
+               status=torch.empty(n, dtype=torch.int32, device=dev),
+               seed_idx=torch.empty(n, dtype=torch.int32, device=dev),
+               n_kept=torch.empty(n, dtype=torch.int32, device=dev),
+               cells=torch.empty(n, dtype=torch.int64, device=dev))
+    lib = _lib.load()
+    _lib.check(lib.xd_align_pairs(
+        store.handle, n, _p(pairs), _p(rc), _p(seed_off), _p(seeds) if n_seeds else None,
+        int(n_seeds), _p(x), int(x_scalar), int(min_dist), int(max_seeds), int(k), int(match),
+        int(mismatch), int(gap), _p(out["score"]), _p(out["beg"]), _p(out["end"]),
+        _p(out["status"]), _p(out["seed_idx"]), _p(out["n_kept"]), _p(out["cells"]),
+        _tuning(tuning), _stream_ptr(stream)))
     return out
 
 

@@ -68,6 +68,7 @@ struct BatchArgs {
   uint32_t* end;
   int32_t* status;
   uint64_t* cells;
+  const uint8_t* flags;  // per task, may be null: bit 0 = B reverse-complemented
 };
 
 // Band tier geometry: each workgroup owns three rows of cap words, cap >
@@ -210,6 +211,16 @@ __device__ __forceinline__ bool make_ext(const BatchArgs& A, uint32_t e, xd::Ext
     ex.ob = (int32_t)pb - 1;
     ex.dir = -1;
   }
+  ex.dirb = ex.dir;
+  ex.comp = 0;
+  const bool rc = A.flags && (__builtin_amdgcn_readfirstlane(A.flags[e >> 1]) & 1u);
+  if (rc) {
+    // B' = complement of B read backwards: position q of B' is lb-1-q of B,
+    // so B is walked the other way from the mirrored start, complemented
+    ex.ob = lb - 1 - ex.ob;
+    ex.dirb = -ex.dir;
+    ex.comp = 3;
+  }
   return true;
 }
 
@@ -333,11 +344,13 @@ struct BinRule {
 // Sort key of extension e, ascending = processing order: first tier from X,
 // then 8 bins per octave of the estimated antidiagonal count (a true overlap
 // extends along the diagonal until the shorter side runs out, about
-// 2*min(m, n) antidiagonals), longest first.  Invalid tasks sort last.
+// 2*min(m, n) antidiagonals), longest first.  Invalid tasks sort at the end
+// of tier 0, where they only write their status.
 __device__ __forceinline__ uint32_t ext_key(const BatchArgs& A, const BinRule& R, uint32_t e) {
   uint32_t ra, rb, pa, pb;
   int32_t X;
-  if (task_status(A, e >> 1, ra, rb, pa, pb, X) != XD_TASK_OK) return kBins - 1;
+  // invalid tasks end tier 0's segment (they only write their status)
+  if (task_status(A, e >> 1, ra, rb, pa, pb, X) != XD_TASK_OK) return kCostBins - 1;
   const uint32_t tier = X <= R.x_tier1 ? 0u : X <= R.x_tier2 ? 1u : 2u;
   if (!R.by_cost) return tier * kCostBins;
   int32_t m, n;
@@ -363,7 +376,7 @@ __global__ __launch_bounds__(256) void k_bin_hist(BatchArgs A, BinRule R, uint32
 
 // hist[b] <- number of extensions with a smaller key (queue start of key b);
 // seg[t] <- queue start of segment t (segments 0..2: first tiers from X;
-// segment 3: invalid tasks), seg[4] = n_ext
+// segment 3 stays empty), seg[4] = n_ext
 __global__ __launch_bounds__(256) void k_bin_scan(uint32_t* hist, uint32_t* seg,
                                                   uint32_t n_ext) {
   __shared__ uint32_t h[kBins];
@@ -429,10 +442,14 @@ __global__ __launch_bounds__(256) void k_combine(BatchArgs A) {
   }
   const uint32_t* wa = A.st.words + A.st.word_off[ra];
   const uint32_t* wb = A.st.words + A.st.word_off[rb];
+  const bool rc = A.flags && (A.flags[t] & 1u);
+  const int32_t lb = (int32_t)A.st.len[rb];
   int32_t seed = 0;
-  for (int32_t u = 0; u < A.k; ++u)
-    seed += (xd::code_at(wa, (int32_t)pa + u) == xd::code_at(wb, (int32_t)pb + u)) ? A.sc.M
-                                                                                    : A.sc.MM;
+  for (int32_t u = 0; u < A.k; ++u) {
+    const uint32_t cb = rc ? 3u - xd::code_at(wb, lb - 1 - ((int32_t)pb + u))
+                           : xd::code_at(wb, (int32_t)pb + u);
+    seed += (xd::code_at(wa, (int32_t)pa + u) == cb) ? A.sc.M : A.sc.MM;
+  }
   A.score[t] = L.best + seed + R.best;
   A.beg[2 * (uint64_t)t] = pa - (uint32_t)L.bi;
   A.beg[2 * (uint64_t)t + 1] = pb - (uint32_t)L.bj;
@@ -440,6 +457,135 @@ __global__ __launch_bounds__(256) void k_combine(BatchArgs A) {
   A.end[2 * (uint64_t)t + 1] = pb + (uint32_t)A.k + (uint32_t)R.bj;
   A.status[t] = XD_TASK_OK;
   if (A.cells) A.cells[t] = L.cells + R.cells;
+}
+
+// ---- multi-seed pairs --------------------------------------------------------
+
+struct PairArgs {
+  uint64_t n_pairs, n_seeds;
+  const uint32_t* pairs;     // [2 n_pairs]
+  const uint8_t* rc;         // [n_pairs] or null
+  const uint64_t* seed_off;  // [n_pairs + 1]
+  const uint32_t* seeds;     // [2 n_seeds]
+  const int32_t* x;          // [n_pairs] or null
+  int32_t x_scalar, min_dist, max_seeds;
+  // one task per listed seed
+  uint32_t* t_pairs;
+  uint32_t* t_seeds;
+  int32_t* t_x;
+  uint8_t* t_flags;
+  int32_t* t_score;
+  uint32_t* t_beg;
+  uint32_t* t_end;
+  int32_t* t_status;
+  uint64_t* t_cells;
+  // per pair
+  int32_t* score;
+  uint32_t* beg;
+  uint32_t* end;
+  int32_t* status;
+  uint32_t* seed_idx;
+  uint32_t* n_kept;
+  uint64_t* cells;
+};
+
+constexpr uint8_t kFlagRc = 1, kFlagKept = 2;
+
+// Seed list of pair p, or false when its range is not inside [0, n_seeds].
+__device__ __forceinline__ bool pair_range(const PairArgs& P, uint64_t p, uint64_t& lo,
+                                           uint64_t& hi) {
+  lo = P.seed_off[p];
+  hi = P.seed_off[p + 1];
+  return lo <= hi && hi <= P.n_seeds;
+}
+
+// every task slot starts invalid (also slots no well-formed range covers)
+__global__ __launch_bounds__(256) void k_pairs_init(PairArgs P) {
+  const uint64_t s = blockIdx.x * 256ull + threadIdx.x;
+  if (s >= P.n_seeds) return;
+  P.t_pairs[2 * s] = 0xffffffffu;
+  P.t_pairs[2 * s + 1] = 0xffffffffu;
+  P.t_seeds[2 * s] = 0;
+  P.t_seeds[2 * s + 1] = 0;
+  P.t_x[s] = -1;
+  P.t_flags[s] = 0;
+}
+
+// One thread per pair: choose its seeds, scanning the list in order and
+// keeping the first seed and each one at least min_dist past the last kept
+// seed's position in A, until max_seeds are kept (0: no limit); then one task
+// per listed seed, with an invalid X for the seeds not kept so that they only
+// write a status.
+__global__ __launch_bounds__(256) void k_pairs_expand(PairArgs P) {
+  const uint64_t p = blockIdx.x * 256ull + threadIdx.x;
+  if (p >= P.n_pairs) return;
+  uint64_t lo, hi;
+  if (!pair_range(P, p, lo, hi)) {
+    P.n_kept[p] = 0;
+    return;
+  }
+  const uint32_t ra = P.pairs[2 * p], rb = P.pairs[2 * p + 1];
+  const uint8_t rc = (P.rc && P.rc[p]) ? kFlagRc : 0;
+  const int32_t X = P.x ? P.x[p] : P.x_scalar;
+  uint32_t kept = 0;
+  int64_t last = 0;
+  for (uint64_t s = lo; s < hi; ++s) {
+    const uint32_t pa = P.seeds[2 * s], pb = P.seeds[2 * s + 1];
+    bool keep = false;
+    if (P.max_seeds == 0 || kept < (uint32_t)P.max_seeds)
+      keep = kept == 0 || (int64_t)pa >= last + P.min_dist;
+    if (keep) {
+      ++kept;
+      last = pa;
+    }
+    P.t_pairs[2 * s] = ra;
+    P.t_pairs[2 * s + 1] = rb;
+    P.t_seeds[2 * s] = pa;
+    P.t_seeds[2 * s + 1] = pb;
+    P.t_x[s] = keep ? X : -1;
+    P.t_flags[s] = (uint8_t)(rc | (keep ? kFlagKept : 0));
+  }
+  P.n_kept[p] = kept;
+}
+
+// One thread per pair: its best kept seed by score (the earliest kept on
+// equal scores).  Until a kept seed aligns, the first kept seed's status
+// stands; with no kept seed the status is XD_TASK_NO_SEED.
+__global__ __launch_bounds__(256) void k_pairs_best(PairArgs P) {
+  const uint64_t p = blockIdx.x * 256ull + threadIdx.x;
+  if (p >= P.n_pairs) return;
+  uint64_t lo, hi;
+  const bool ok_range = pair_range(P, p, lo, hi);
+  int32_t st = ok_range ? XD_TASK_NO_SEED : XD_TASK_BAD_SEED;
+  bool seen = false;
+  int32_t best = INT32_MIN;
+  uint64_t bs = 0, cells = 0;
+  if (ok_range) {
+    for (uint64_t s = lo; s < hi; ++s) {
+      if (!(P.t_flags[s] & kFlagKept)) continue;
+      cells += P.t_cells[s];
+      const int32_t ts = P.t_status[s];
+      if (!seen) {
+        st = ts;
+        seen = true;
+      }
+      if (ts != XD_TASK_OK) continue;
+      if (st != XD_TASK_OK || P.t_score[s] > best) {
+        st = XD_TASK_OK;
+        best = P.t_score[s];
+        bs = s;
+      }
+    }
+  }
+  const bool ok = st == XD_TASK_OK;
+  P.score[p] = ok ? best : INT32_MIN;
+  P.beg[2 * p] = ok ? P.t_beg[2 * bs] : 0u;
+  P.beg[2 * p + 1] = ok ? P.t_beg[2 * bs + 1] : 0u;
+  P.end[2 * p] = ok ? P.t_end[2 * bs] : 0u;
+  P.end[2 * p + 1] = ok ? P.t_end[2 * bs + 1] : 0u;
+  P.status[p] = st;
+  P.seed_idx[p] = ok ? (uint32_t)(bs - lo) : 0xffffffffu;
+  P.cells[p] = cells;
 }
 
 // ---- launch sequences -------------------------------------------------------
@@ -459,9 +605,8 @@ int device_cus() {
 
 // tier arguments: tier 0 (64 cells, batched form), tiers 1..4 (128, 256, 512,
 // 1024 cells) and the band tier, each with its queue segment (batched form;
-// segments 0..2 hold the extensions whose X picks that first tier, segment 3
-// the invalid tasks, which tier 3 marks) and the overflow list of the tier
-// below
+// segments 0..2 hold the extensions whose X picks that first tier) and the
+// overflow list of the tier below
 TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
   uint32_t* c = S.ctr;
   TierPack p;
@@ -665,6 +810,7 @@ int make_args(const xd_store* store, const uint32_t* pairs, const uint32_t* seed
   A.end = end;
   A.status = status;
   A.cells = cells;
+  A.flags = nullptr;
   return XD_OK;
 }
 
@@ -874,6 +1020,97 @@ int xd_align_batch_persistent(const xd_store* store, const uint32_t* pairs,
   if (rc) return rc;
   if (n == 0) return XD_OK;
   return batch_async(A, store->max_len, true, tu, (hipStream_t)hip_stream);
+}
+
+int xd_align_pairs(const xd_store* store, uint64_t n_pairs, const uint32_t* pairs,
+                   const uint8_t* rc, const uint64_t* seed_off, const uint32_t* seeds,
+                   uint64_t n_seeds, const int32_t* x, int32_t x_scalar, int32_t min_dist,
+                   int32_t max_seeds, int32_t k, int32_t match, int32_t mismatch, int32_t gap,
+                   int32_t* score, uint32_t* beg, uint32_t* end, int32_t* status,
+                   uint32_t* seed_idx, uint32_t* n_kept, uint64_t* cells,
+                   const xd_tuning* tuning, void* hip_stream) {
+  if (!store) return fail(XD_EINVAL, "xd_align_pairs: store is null");
+  int rc_ = check_scoring(k, match, mismatch, gap);
+  if (rc_) return rc_;
+  if (!x && (x_scalar < 0 || x_scalar > XD_X_MAX))
+    return fail(XD_EINVAL, "x_scalar must be in [0, %d] (got %d)", XD_X_MAX, x_scalar);
+  if (min_dist < 0 || max_seeds < 0)
+    return fail(XD_EINVAL, "xd_align_pairs: min_dist and max_seeds must be >= 0");
+  if (n_pairs > (1ull << 30) || n_seeds > (1ull << 30))
+    return fail(XD_EINVAL, "xd_align_pairs: at most 2^30 pairs and 2^30 seeds");
+  if (n_pairs && (!pairs || !seed_off || !score || !beg || !end || !status || !seed_idx ||
+                  !n_kept || !cells))
+    return fail(XD_EINVAL, "xd_align_pairs: null pair or result array");
+  if (n_seeds && !seeds) return fail(XD_EINVAL, "xd_align_pairs: seeds is null");
+  Tuned tu;
+  rc_ = check_tuning(tuning, tu);
+  if (rc_) return rc_;
+  if (n_pairs == 0) return XD_OK;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  const BandGeom g = band_geom(store->max_len, (uint32_t)tu.band_blocks);
+  const uint64_t S = n_seeds;
+  auto al = [](uint64_t b) { return (b + 255) & ~255ull; };
+  const uint64_t task_bytes = al(8 * S) * 2 + al(4 * S) + al(S) + al(4 * S) + al(8 * S) * 2 +
+                              al(4 * S) + al(8 * S);
+  const uint64_t batch_bytes = S ? scratch_bytes(S, g) : 0;
+  char* mem = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&mem, task_bytes + batch_bytes + 256, stream));
+  char* q = mem;
+  auto take = [&](uint64_t b) {
+    char* r = q;
+    q += al(b);
+    return r;
+  };
+  PairArgs P;
+  P.n_pairs = n_pairs;
+  P.n_seeds = S;
+  P.pairs = pairs;
+  P.rc = rc;
+  P.seed_off = seed_off;
+  P.seeds = seeds;
+  P.x = x;
+  P.x_scalar = x_scalar;
+  P.min_dist = min_dist;
+  P.max_seeds = max_seeds;
+  P.t_pairs = (uint32_t*)take(8 * S);
+  P.t_seeds = (uint32_t*)take(8 * S);
+  P.t_x = (int32_t*)take(4 * S);
+  P.t_flags = (uint8_t*)take(S);
+  P.t_score = (int32_t*)take(4 * S);
+  P.t_beg = (uint32_t*)take(8 * S);
+  P.t_end = (uint32_t*)take(8 * S);
+  P.t_status = (int32_t*)take(4 * S);
+  P.t_cells = (uint64_t*)take(8 * S);
+  P.score = score;
+  P.beg = beg;
+  P.end = end;
+  P.status = status;
+  P.seed_idx = seed_idx;
+  P.n_kept = n_kept;
+  P.cells = cells;
+  const uint32_t pgrid = (uint32_t)((n_pairs + 255) / 256);
+  if (S) {
+    hipLaunchKernelGGL(k_pairs_init, dim3((uint32_t)((S + 255) / 256)), dim3(256), 0, stream, P);
+  }
+  hipLaunchKernelGGL(k_pairs_expand, dim3(pgrid), dim3(256), 0, stream, P);
+  int rc2 = XD_OK;
+  if (S) {
+    BatchArgs A;
+    rc2 = make_args(store, P.t_pairs, P.t_seeds, P.t_x, 0, S, k, match, mismatch, gap,
+                    P.t_score, P.t_beg, P.t_end, P.t_status, P.t_cells, A);
+    if (rc2 == XD_OK) {
+      A.flags = P.t_flags;
+      rc2 = enqueue(A, scratch_carve(q, S, g), true, tu, stream, true);
+    }
+  }
+  if (rc2 == XD_OK)
+    hipLaunchKernelGGL(k_pairs_best, dim3(pgrid), dim3(256), 0, stream, P);
+  hipError_t fe = hipFreeAsync(mem, stream);
+  if (rc2) return rc2;
+  if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
+  hipError_t le = hipGetLastError();
+  if (le != hipSuccess) return hip_fail(le, "kernel launch");
+  return XD_OK;
 }
 
 int xd_plan_create(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,

@@ -63,7 +63,9 @@ struct Ext {
   const uint32_t* wa;  // first word of read A
   const uint32_t* wb;  // first word of read B
   int32_t oa, ob;      // position of a_1 in A, of b_1 in B
-  int32_t dir;         // +1 (right extension) or -1 (left, reads backwards)
+  int32_t dir;         // step through A: +1 (right extension) or -1 (left, backwards)
+  int32_t dirb;        // step through B (the reverse of dir when B is reverse-complemented)
+  uint32_t comp;       // 3 when B is reverse-complemented (code ^ 3 = complement), else 0
   int32_t m, n;        // characters available in a and b
   int32_t X;
 };
@@ -251,27 +253,29 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
   constexpr int RA = TI::RA;
   uint8_t* aring = (uint8_t*)(ring + RING + MIR);
 
-  // packed word holding position p of a read, or 0 outside [lo, hi]
-  auto word_of = [&](const uint32_t* w, int32_t o, int32_t q, int32_t lim) -> uint32_t {
+  // packed word holding character q (1-based) of a or b, or 0 outside [1, lim]
+  auto word_of = [&](const uint32_t* w, int32_t o, int32_t dr, int32_t q,
+                     int32_t lim) -> uint32_t {
     uint32_t v = 0;
-    if (q >= 1 & q <= lim) v = w[(o + e.dir * (q - 1)) >> 4];
+    if (q >= 1 & q <= lim) v = w[(o + dr * (q - 1)) >> 4];
     return v;
   };
-  auto code_in = [&](uint32_t w, int32_t o, int32_t q) -> uint32_t {
-    return (w >> (((o + e.dir * (q - 1)) & 15) << 1)) & 3u;
+  auto code_in = [&](uint32_t w, int32_t o, int32_t dr, int32_t q) -> uint32_t {
+    return (w >> (((o + dr * (q - 1)) & 15) << 1)) & 3u;
   };
 
   // b ring: chunk c holds j in [64c, 64c+63]; pf_b carries the next chunk
   int32_t filled = -1;  // highest j whose ring slot holds b_j
-  uint32_t pf_b = word_of(e.wb, e.ob, lane, n);
+  uint32_t pf_b = word_of(e.wb, e.ob, e.dirb, lane, n);
   auto fill_to = [&](int32_t jhi) {
     while (filled < jhi) {
       const int32_t j = filled + 1 + lane;
-      const uint32_t v = (j >= 1 & j <= n) ? (dM << (8u * code_in(pf_b, e.ob, j))) : 0u;
+      const uint32_t v =
+          (j >= 1 & j <= n) ? (dM << (8u * (code_in(pf_b, e.ob, e.dirb, j) ^ e.comp))) : 0u;
       const int slot = j & MASK;
       ring[slot] = v;
       if (slot < MIR) ring[RING + slot] = v;
-      pf_b = word_of(e.wb, e.ob, j + 64, n);  // the chunk after, on its way
+      pf_b = word_of(e.wb, e.ob, e.dirb, j + 64, n);  // the chunk after, on its way
       filled += 64;
     }
     wave_lds_fence();
@@ -279,12 +283,12 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
 
   // a ring: chunk c holds i in [64c, 64c+63] (code 0 outside 1..m)
   int32_t filled_a = -1;
-  uint32_t pf_a = word_of(e.wa, e.oa, lane, m);
+  uint32_t pf_a = word_of(e.wa, e.oa, e.dir, lane, m);
   auto fill_a_to = [&](int32_t ihi) {
     while (filled_a < ihi) {
       const int32_t i = filled_a + 1 + lane;
-      aring[i & (RA - 1)] = (uint8_t)((i >= 1 & i <= m) ? code_in(pf_a, e.oa, i) : 0u);
-      pf_a = word_of(e.wa, e.oa, i + 64, m);
+      aring[i & (RA - 1)] = (uint8_t)((i >= 1 & i <= m) ? code_in(pf_a, e.oa, e.dir, i) : 0u);
+      pf_a = word_of(e.wa, e.oa, e.dir, i + 64, m);
       filled_a += 64;
     }
     wave_lds_fence();
@@ -719,7 +723,8 @@ __device__ __forceinline__ void extend_band(const Ext& e, const Scoring& sc,
         const int32_t dg = (i - 1 >= wlo2 && i - 1 <= whi2) ? r2[i - 1] : 0;
         int32_t bonus = 0;
         if (i >= 1 && j >= 1 &&
-            code_at(e.wa, e.oa + e.dir * (i - 1)) == code_at(e.wb, e.ob + e.dir * (j - 1)))
+            code_at(e.wa, e.oa + e.dir * (i - 1)) ==
+                (code_at(e.wb, e.ob + e.dirb * (j - 1)) ^ e.comp))
           bonus = dM;
         s = max(max(dg + bonus + C, up), left);
         cnt += (s > kEvMin) ? 1u : 0u;
