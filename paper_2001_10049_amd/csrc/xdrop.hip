@@ -344,13 +344,14 @@ struct BinRule {
 // Sort key of extension e, ascending = processing order: first tier from X,
 // then 8 bins per octave of the estimated antidiagonal count (a true overlap
 // extends along the diagonal until the shorter side runs out, about
-// 2*min(m, n) antidiagonals), longest first.  Invalid tasks sort at the end
-// of tier 0, where they only write their status.
+// 2*min(m, n) antidiagonals), longest first.  Invalid tasks sort last, into
+// a segment that is never run.
 __device__ __forceinline__ uint32_t ext_key(const BatchArgs& A, const BinRule& R, uint32_t e) {
   uint32_t ra, rb, pa, pb;
   int32_t X;
-  // invalid tasks end tier 0's segment (they only write their status)
-  if (task_status(A, e >> 1, ra, rb, pa, pb, X) != XD_TASK_OK) return kCostBins - 1;
+  // invalid tasks go to segment 3, which no tier runs: the combine writes
+  // their status without reading extension results
+  if (task_status(A, e >> 1, ra, rb, pa, pb, X) != XD_TASK_OK) return kBins - 1;
   const uint32_t tier = X <= R.x_tier1 ? 0u : X <= R.x_tier2 ? 1u : 2u;
   if (!R.by_cost) return tier * kCostBins;
   int32_t m, n;
@@ -376,7 +377,7 @@ __global__ __launch_bounds__(256) void k_bin_hist(BatchArgs A, BinRule R, uint32
 
 // hist[b] <- number of extensions with a smaller key (queue start of key b);
 // seg[t] <- queue start of segment t (segments 0..2: first tiers from X;
-// segment 3 stays empty), seg[4] = n_ext
+// segment 3: invalid tasks, never run), seg[4] = n_ext
 __global__ __launch_bounds__(256) void k_bin_scan(uint32_t* hist, uint32_t* seg,
                                                   uint32_t n_ext) {
   __shared__ uint32_t h[kBins];
@@ -427,9 +428,14 @@ __global__ __launch_bounds__(256) void k_combine(BatchArgs A) {
   uint32_t ra, rb, pa, pb;
   int32_t X;
   int32_t st = task_status(A, t, ra, rb, pa, pb, X);
-  const ExtOut L = A.ext[2 * (uint64_t)t];
-  const ExtOut R = A.ext[2 * (uint64_t)t + 1];
-  if (st == XD_TASK_OK && ((L.flags | R.flags) & xd::kExtOverflow)) st = XD_TASK_BAND_OVERFLOW;
+  // extension results exist only for valid tasks (the batched form never
+  // runs the invalid ones)
+  ExtOut L = {0, 0, 0, 0, 0}, R = {0, 0, 0, 0, 0};
+  if (st == XD_TASK_OK) {
+    L = A.ext[2 * (uint64_t)t];
+    R = A.ext[2 * (uint64_t)t + 1];
+    if ((L.flags | R.flags) & xd::kExtOverflow) st = XD_TASK_BAND_OVERFLOW;
+  }
   if (st != XD_TASK_OK) {
     A.score[t] = INT32_MIN;
     A.beg[2 * (uint64_t)t] = 0;
@@ -616,8 +622,8 @@ TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
             c + kHead + 1, S.ovf[1], c + kOvfCount + 1};
   p.t[2] = {A, S.queue, segs ? c + kSeg + 2 : nullptr, S.ovf[1], c + kOvfCount + 1,
             c + kHead + 2, S.ovf[2], c + kOvfCount + 2};
-  p.t[3] = {A, S.queue, segs ? c + kSeg + 3 : nullptr, S.ovf[2], c + kOvfCount + 2,
-            c + kHead + 3, S.ovf[3], c + kOvfCount + 3};
+  p.t[3] = {A, S.queue, nullptr, S.ovf[2], c + kOvfCount + 2, c + kHead + 3, S.ovf[3],
+            c + kOvfCount + 3};
   p.t[4] = {A, S.queue, nullptr, S.ovf[3], c + kOvfCount + 3, c + kHead + 4, S.ovf[4],
             c + kOvfCount + 4};
   p.t[5] = {A, S.queue, nullptr, S.ovf[4], c + kOvfCount + 4, c + kBandHead, nullptr, nullptr};
