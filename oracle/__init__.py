@@ -21,6 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "xdrop_oracle.c")
+_SRC_BANDED = os.path.join(_HERE, "banded_oracle.c")
 _HDR = os.path.join(_HERE, "xdrop_oracle.h")
 
 TASK_OK, TASK_BAD_READ, TASK_BAD_SEED, TASK_BAD_X = 0, 1, 2, 3
@@ -30,11 +31,11 @@ X_INF = 1 << 40  # no pruning
 
 def build_lib(force: bool = False) -> str:
     """Compile the oracle (plain C, gcc) next to its source."""
-    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_HDR))
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_BANDED), os.path.getmtime(_HDR))
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < newest:
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
-                               "-o", tmp, _SRC])
+                               "-o", tmp, _SRC, _SRC_BANDED])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -55,6 +56,19 @@ class _Task(ctypes.Structure):
                 ("end_b", ctypes.c_uint32), ("cells", ctypes.c_uint64),
                 ("status", ctypes.c_int32)]
 
+
+class _Banded(ctypes.Structure):
+    _fields_ = [("best", ctypes.c_int64), ("i", ctypes.c_int64), ("j", ctypes.c_int64),
+                ("cells", ctypes.c_uint64)]
+
+
+class _BandedTask(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_int32), ("end_a", ctypes.c_uint32),
+                ("end_b", ctypes.c_uint32), ("cells", ctypes.c_uint64),
+                ("status", ctypes.c_int32)]
+
+
+BAND_MAX = 55
 
 _lib = None
 
@@ -79,6 +93,14 @@ def _load():
                                        ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp,
                                        ctypes.c_int]
+        lib.xo_banded.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, ctypes.c_int64,
+                                  ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.POINTER(_Banded)]
+        lib.xo_banded_task.argtypes = [vp, vp, vp, ctypes.c_uint32, ctypes.c_uint32,
+                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(_BandedTask)]
         _lib = lib
     return _lib
 
@@ -177,3 +199,41 @@ def align_workload(w, x=None, n_threads=None, **kw):
     res, _ = align_batch(w.codes, w.off, w.length, pairs, seeds,
                          x=w.x if x is None else x, k=w.k, n_threads=n_threads, **kw)
     return res
+
+
+def banded(a, b, c, w, match=1, mismatch=-1, gap=-1):
+    """Banded Smith-Waterman (banded_oracle.c) -> (best, i, j, cells)."""
+    a, b = _u8(a), _u8(b)
+    pa = a if a.size else np.zeros(1, np.uint8)
+    pb = b if b.size else np.zeros(1, np.uint8)
+    r = _Banded()
+    if _load().xo_banded(_p(pa), a.size, _p(pb), b.size, int(c), int(w), match, mismatch, gap,
+                         ctypes.byref(r)):
+        raise MemoryError("banded oracle failed")
+    return int(r.best), int(r.i), int(r.j), int(r.cells)
+
+
+def banded_batch(codes, off, length, pairs, seeds, w, k=17, match=1, mismatch=-1, gap=-1):
+    """Banded tasks (band around each seed's diagonal) -> dict(score, end[n, 2],
+    cells, status); w: one half-width or one per task."""
+    codes = np.ascontiguousarray(codes, np.uint8)
+    off = np.ascontiguousarray(off, np.uint64)
+    length = np.ascontiguousarray(length, np.uint32)
+    pairs = np.asarray(pairs, np.uint32).reshape(-1, 2)
+    seeds = np.asarray(seeds, np.uint32).reshape(-1, 2)
+    n = pairs.shape[0]
+    ws = np.broadcast_to(np.asarray(w, np.int64), (n,))
+    out = dict(score=np.zeros(n, np.int32), end=np.zeros((n, 2), np.uint32),
+               cells=np.zeros(n, np.uint64), status=np.zeros(n, np.int32))
+    lib = _load()
+    r = _BandedTask()
+    for t in range(n):
+        if lib.xo_banded_task(_p(codes), _p(off), _p(length), length.size, int(pairs[t, 0]),
+                              int(pairs[t, 1]), int(seeds[t, 0]), int(seeds[t, 1]), int(ws[t]),
+                              k, match, mismatch, gap, ctypes.byref(r)):
+            raise ValueError("banded oracle rejected the task parameters")
+        out["score"][t] = r.score
+        out["end"][t] = (r.end_a, r.end_b)
+        out["cells"][t] = r.cells
+        out["status"][t] = r.status
+    return out

@@ -1,0 +1,110 @@
+/*
+ * Reference banded Smith-Waterman: TEST INFRASTRUCTURE ONLY.  Only the
+ * test-suite and the benchmark's CPU-baseline leg use it; the product library
+ * shares no code with it.
+ *
+ * Section 2 of the paper names, besides the X-drop rule, the search for
+ * alignments with a limited number of mismatches (banded Smith-Waterman) as
+ * the way to make pairwise alignment linear in the read length.  Reading used
+ * here (the paper gives no further detail): local alignment with linear gaps
+ * of a[1..m] against b[1..n], restricted to the cells within w of one
+ * diagonal (the seed's, c = pa - pb):
+ *
+ *   H(i,0) = H(0,j) = 0
+ *   for 1 <= i <= m, 1 <= j <= n, |i - j - c| <= w:
+ *     H(i,j) = max(0, H(i-1,j-1) + s(a_i,b_j), H(i-1,j) + gap, H(i,j-1) + gap)
+ *   where a neighbour outside the band contributes nothing.
+ *
+ * best = the largest H, reached first (smallest i + j, then smallest i) at the
+ * end cell (i*, j*); best = 0 with end (0, 0) when no cell is positive.
+ * cells = the number of band cells inside the grid.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+
+#include "xdrop_oracle.h"
+
+int xo_banded(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, int64_t c, int64_t w,
+              int32_t match, int32_t mismatch, int32_t gap, xo_banded_result* out) {
+  /* rows i-1 and i of H, row-major, NEG outside the band; row and column 0
+     hold the boundary zeros (plain and slow) */
+  const int64_t NEG = INT64_MIN / 4;
+  int64_t* prev = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  int64_t* cur = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  if (!prev || !cur) {
+    free(prev);
+    free(cur);
+    return -1;
+  }
+  for (int64_t j = 0; j <= n; ++j) prev[j] = 0; /* row 0 */
+  int64_t best = 0, bi = 0, bj = 0;
+  uint64_t cells = 0;
+  for (int64_t i = 1; i <= m; ++i) {
+    cur[0] = 0; /* column 0 */
+    for (int64_t j = 1; j <= n; ++j) {
+      const int64_t off = i - j - c;
+      if (off < -w || off > w) {
+        cur[j] = NEG;
+        continue;
+      }
+      ++cells;
+      const int64_t s = (a[i - 1] == b[j - 1]) ? match : mismatch;
+      int64_t h = 0;
+      const int64_t dg = prev[j - 1], up = prev[j], lf = cur[j - 1];
+      if (dg > NEG && dg + s > h) h = dg + s;
+      if (up > NEG && up + gap > h) h = up + gap;
+      if (lf > NEG && lf + gap > h) h = lf + gap;
+      cur[j] = h;
+      /* first reached: smaller antidiagonal i + j, then smaller i */
+      if (h > best || (h == best && h > 0 &&
+                       (i + j < bi + bj || (i + j == bi + bj && i < bi)))) {
+        best = h;
+        bi = i;
+        bj = j;
+      }
+    }
+    int64_t* t = prev;
+    prev = cur;
+    cur = t;
+  }
+  free(prev);
+  free(cur);
+  out->best = best;
+  out->i = bi;
+  out->j = bj;
+  out->cells = cells;
+  return 0;
+}
+
+int xo_banded_task(const uint8_t* codes, const uint64_t* off, const uint32_t* len,
+                   uint32_t n_reads, uint32_t ra, uint32_t rb, uint32_t pa, uint32_t pb,
+                   int32_t w, int32_t k, int32_t match, int32_t mismatch, int32_t gap,
+                   xo_banded_task_result* out) {
+  out->score = INT32_MIN;
+  out->end_a = out->end_b = 0;
+  out->cells = 0;
+  if (xo_check_params(k, match, mismatch, gap)) return -1;
+  if (ra >= n_reads || rb >= n_reads) {
+    out->status = XO_TASK_BAD_READ;
+    return 0;
+  }
+  const uint64_t la = len[ra], lb = len[rb];
+  if ((uint64_t)pa + (uint64_t)k > la || (uint64_t)pb + (uint64_t)k > lb) {
+    out->status = XO_TASK_BAD_SEED;
+    return 0;
+  }
+  if (w < 0 || w > XO_BAND_MAX) {
+    out->status = XO_TASK_BAD_X;
+    return 0;
+  }
+  xo_banded_result r;
+  if (xo_banded(codes + off[ra], (int64_t)la, codes + off[rb], (int64_t)lb,
+                (int64_t)pa - (int64_t)pb, w, match, mismatch, gap, &r))
+    return -1;
+  out->score = (int32_t)r.best;
+  out->end_a = (uint32_t)r.i;
+  out->end_b = (uint32_t)r.j;
+  out->cells = r.cells;
+  out->status = XO_TASK_OK;
+  return 0;
+}

@@ -65,6 +65,35 @@ int xo_align_batch(const uint8_t* codes, const uint64_t* off, const uint32_t* le
                    int32_t mismatch, int32_t gap, int32_t* score, uint32_t* beg, uint32_t* end,
                    int32_t* status, uint64_t* cells, int n_threads);
 
+/* Banded Smith-Waterman (banded_oracle.c): band half-width limit */
+#define XO_BAND_MAX 55
+
+typedef struct {
+  int64_t best;   /* best local score (>= 0) */
+  int64_t i, j;   /* its end cell, (0, 0) when best = 0 */
+  uint64_t cells; /* band cells inside the grid */
+} xo_banded_result;
+
+typedef struct {
+  int32_t score;
+  uint32_t end_a, end_b; /* half-open ends of the best local alignment */
+  uint64_t cells;
+  int32_t status;        /* XO_TASK_BAD_X: w outside [0, XO_BAND_MAX] */
+} xo_banded_task_result;
+
+/* Banded local alignment of a[0..m) and b[0..n) within |i - j - c| <= w
+   (1-based i, j).  Returns 0, or -1 when out of memory. */
+int xo_banded(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, int64_t c, int64_t w,
+              int32_t match, int32_t mismatch, int32_t gap, xo_banded_result* out);
+
+/* One banded task: reads ra, rb of the read set, band around the diagonal of
+   the seed (pa, pb) (c = pa - pb).  Returns 0, or -1 on bad scoring or out of
+   memory. */
+int xo_banded_task(const uint8_t* codes, const uint64_t* off, const uint32_t* len,
+                   uint32_t n_reads, uint32_t ra, uint32_t rb, uint32_t pa, uint32_t pb,
+                   int32_t w, int32_t k, int32_t match, int32_t mismatch, int32_t gap,
+                   xo_banded_task_result* out);
+
 #ifdef __cplusplus
 }
 #endif
