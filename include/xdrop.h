@@ -194,6 +194,31 @@ int xd_align_pairs(const xd_store* store, uint64_t n_pairs, const uint32_t* pair
                    uint32_t* seed_idx, uint32_t* n_kept, uint64_t* cells,
                    const xd_tuning* tuning, void* hip_stream);
 
+/* ---- banded Smith-Waterman ----------------------------------------------- */
+
+#define XD_BAND_MAX 48 /* largest band half-width w */
+
+/* Banded local alignment (paper section 2 names banded Smith-Waterman, a
+ * search with a limited number of mismatches, beside X-drop): for task t,
+ * reads A = pairs[2t], B = pairs[2t+1] and seed (pa, pb) = seeds[2t..2t+1]
+ * (checked as for xd_align_batch: pa + k <= |A|, pb + k <= |B|), with 1-based
+ * cells (i, j) of A x B and the band |i - j - (pa - pb)| <= w:
+ *   H(i,0) = H(0,j) = 0
+ *   H(i,j) = max(0, H(i-1,j-1) + s(a_i,b_j), H(i-1,j) + gap, H(i,j-1) + gap)
+ * for band cells, a neighbour outside the band contributing nothing.
+ *   score  int32[n]    the largest H (>= 0); INT32_MIN when status != 0
+ *   end    uint32[2n]  its cell (i, j), first reached (smallest i + j, then
+ *                      smallest i) = half-open end of the best local alignment
+ *                      in A and B; (0, 0) when score is 0
+ *   status int32[n]    XD_TASK_*; XD_TASK_BAD_X: w outside [0, XD_BAND_MAX]
+ *   cells  uint64[n]   may be NULL; band cells inside the grid
+ * w: int32[n] half-widths, or NULL to use w_scalar.  Device pointers,
+ * asynchronous on hip_stream; one wavefront per task. */
+int xd_banded_batch(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,
+                    const int32_t* w, int32_t w_scalar, uint64_t n, int32_t k, int32_t match,
+                    int32_t mismatch, int32_t gap, int32_t* score, uint32_t* end,
+                    int32_t* status, uint64_t* cells, void* hip_stream);
+
 /* A captured batch: the batched form's kernels recorded once in a hipGraph
  * for fixed buffers (same meaning as xd_align_batch's) and replayed by
  * xd_plan_launch.  The plan owns its scratch memory.  Between launches the

@@ -68,7 +68,7 @@ class _BandedTask(ctypes.Structure):
                 ("status", ctypes.c_int32)]
 
 
-BAND_MAX = 55
+BAND_MAX = 48
 
 _lib = None
 

@@ -26,27 +26,30 @@
 
 int xo_banded(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, int64_t c, int64_t w,
               int32_t match, int32_t mismatch, int32_t gap, xo_banded_result* out) {
-  /* rows i-1 and i of H, row-major, NEG outside the band; row and column 0
-     hold the boundary zeros (plain and slow) */
+  /* rows i-1 and i of H (plain and slow).  Row i's band is the columns
+     j in [i-c-w, i-c+w]; the entries a row reads just outside it (the
+     neighbours (i-1, j) and (i, j-1) one column beyond the band) are set to
+     NEG before the row is computed, and row 0 / column 0 hold the zeros. */
   const int64_t NEG = INT64_MIN / 4;
-  int64_t* prev = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
-  int64_t* cur = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  int64_t* prev = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 2));
+  int64_t* cur = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 2));
   if (!prev || !cur) {
     free(prev);
     free(cur);
     return -1;
   }
-  for (int64_t j = 0; j <= n; ++j) prev[j] = 0; /* row 0 */
+  for (int64_t j = 0; j <= n + 1; ++j) prev[j] = 0; /* row 0 */
   int64_t best = 0, bi = 0, bj = 0;
   uint64_t cells = 0;
   for (int64_t i = 1; i <= m; ++i) {
+    int64_t jlo = i - c - w, jhi = i - c + w;
+    if (jlo < 1) jlo = 1;
+    if (jhi > n) jhi = n;
+    /* the previous row's entry one past its band end, read as (i-1, jhi) */
+    if (jhi >= 1 && i - 1 >= 1 && jhi > (i - 1) - c + w) prev[jhi] = NEG;
+    for (int64_t j = (jlo - 1 > 0 ? jlo - 1 : 0); j <= jhi + 1 && j <= n + 1; ++j) cur[j] = NEG;
     cur[0] = 0; /* column 0 */
-    for (int64_t j = 1; j <= n; ++j) {
-      const int64_t off = i - j - c;
-      if (off < -w || off > w) {
-        cur[j] = NEG;
-        continue;
-      }
+    for (int64_t j = jlo; j <= jhi; ++j) {
       ++cells;
       const int64_t s = (a[i - 1] == b[j - 1]) ? match : mismatch;
       int64_t h = 0;

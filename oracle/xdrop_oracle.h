@@ -66,7 +66,7 @@ int xo_align_batch(const uint8_t* codes, const uint64_t* off, const uint32_t* le
                    int32_t* status, uint64_t* cells, int n_threads);
 
 /* Banded Smith-Waterman (banded_oracle.c): band half-width limit */
-#define XO_BAND_MAX 55
+#define XO_BAND_MAX 48
 
 typedef struct {
   int64_t best;   /* best local score (>= 0) */

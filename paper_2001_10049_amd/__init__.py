@@ -12,8 +12,8 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (READ_MAX, SCORE_LIMIT, TASK_BAD_READ, TASK_BAD_SEED, TASK_BAD_X,  # noqa
-                   TASK_BAND_OVERFLOW, TASK_NO_SEED, TASK_OK, X_MAX, XdropError)
+from ._lib import (BAND_MAX, READ_MAX, SCORE_LIMIT, TASK_BAD_READ, TASK_BAD_SEED,  # noqa
+                   TASK_BAD_X, TASK_BAND_OVERFLOW, TASK_NO_SEED, TASK_OK, X_MAX, XdropError)
 
 
 def _p(a) -> ctypes.c_void_p:
@@ -163,6 +163,31 @@ def align_batch(store: ReadStore, pairs, seeds, x=None, x_scalar=0, k=17, match=
         _lib.check(lib.xd_align_batch_persistent(*args, _tuning(tuning), _stream_ptr(stream)))
     else:
         _lib.check(lib.xd_align_batch(*args, _stream_ptr(stream)))
+    return out
+
+
+def banded_batch(store: ReadStore, pairs, seeds, w=None, w_scalar=32, k=17, match=1,
+                 mismatch=-1, gap=-1, stream=None):
+    """Banded Smith-Waterman (xd_banded_batch) around each seed's diagonal.
+
+    pairs, seeds: [n, 2] 4-byte device tensors; w: int32 [n] or None.  Returns
+    dict(score int32 [n], end int32 [n, 2], status int32 [n], cells int64 [n])."""
+    import torch
+    n = int(pairs.shape[0])
+    dev = pairs.device
+    _check_dev("pairs", pairs, 2 * n, 4)
+    _check_dev("seeds", seeds, 2 * n, 4)
+    if w is not None:
+        _check_dev("w", w, n, 4)
+    out = dict(score=torch.empty(n, dtype=torch.int32, device=dev),
+               end=torch.empty((n, 2), dtype=torch.int32, device=dev),
+               status=torch.empty(n, dtype=torch.int32, device=dev),
+               cells=torch.empty(n, dtype=torch.int64, device=dev))
+    lib = _lib.load()
+    _lib.check(lib.xd_banded_batch(store.handle, _p(pairs), _p(seeds), _p(w), int(w_scalar), n,
+                                   int(k), int(match), int(mismatch), int(gap), _p(out["score"]),
+                                   _p(out["end"]), _p(out["status"]), _p(out["cells"]),
+                                   _stream_ptr(stream)))
     return out
 
 

@@ -11,6 +11,7 @@ XD_OK, XD_EINVAL, XD_ENOMEM, XD_EDEVICE, XD_EAGAIN = 0, -1, -2, -3, -4
 TASK_OK, TASK_BAD_READ, TASK_BAD_SEED, TASK_BAD_X, TASK_BAND_OVERFLOW = 0, 1, 2, 3, 4
 TASK_NO_SEED = 5
 X_MAX = 1 << 20
+BAND_MAX = 48
 SCORE_LIMIT = 127
 READ_MAX = 1 << 22
 
@@ -18,6 +19,7 @@ READ_MAX = 1 << 22
 EXPORTS = (
     "xd_pack_reads", "xd_store_create", "xd_store_create_from_codes", "xd_store_destroy",
     "xd_store_info", "xd_align_batch", "xd_align_batch_persistent", "xd_align_pairs",
+    "xd_banded_batch",
     "xd_plan_create",
     "xd_plan_launch", "xd_plan_destroy", "xd_profile_enable", "xd_profile_read",
     "xd_server_request_bytes", "xd_server_fixed_bytes", "xd_server_create", "xd_server_submit", "xd_server_poll",
@@ -102,6 +104,9 @@ def load() -> ctypes.CDLL:
                                    i32, i32, vp, vp, vp, vp, vp, vp, vp,
                                    ctypes.POINTER(Tuning), vp]
     lib.xd_align_pairs.restype = ctypes.c_int
+    lib.xd_banded_batch.argtypes = [vp, vp, vp, vp, i32, u64, i32, i32, i32, i32, vp, vp, vp,
+                                    vp, vp]
+    lib.xd_banded_batch.restype = ctypes.c_int
     lib.xd_plan_create.argtypes = batch + [ctypes.POINTER(Tuning), ctypes.POINTER(vp)]
     lib.xd_plan_create.restype = ctypes.c_int
     lib.xd_plan_launch.argtypes = [vp, vp]

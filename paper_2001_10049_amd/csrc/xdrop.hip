@@ -148,6 +148,7 @@ struct TierArgs {
 };
 
 static_assert(6 * sizeof(TierArgs) <= kTierArgsBytes, "tier argument area");
+static_assert(xd::kBandedMaxW == XD_BAND_MAX, "band limit");
 static_assert(sizeof(TierArgs) % 4 == 0, "tier arguments copied by words");
 
 struct TierPack {
@@ -592,6 +593,70 @@ __global__ __launch_bounds__(256) void k_pairs_best(PairArgs P) {
   P.status[p] = st;
   P.seed_idx[p] = ok ? (uint32_t)(bs - lo) : 0xffffffffu;
   P.cells[p] = cells;
+}
+
+// ---- banded Smith-Waterman ---------------------------------------------------
+
+struct BandedArgs {
+  StoreDev st;
+  const uint32_t* pairs;
+  const uint32_t* seeds;
+  const int32_t* w;
+  int32_t w_scalar;
+  uint32_t n;
+  int32_t k;
+  xd::Scoring sc;
+  int32_t* score;
+  uint32_t* end;
+  int32_t* status;
+  uint64_t* cells;
+};
+
+constexpr int kBandedLdsWords = 256 + 17 + 32;
+
+// One wavefront per task: band around the seed's diagonal over the whole reads.
+template <bool UNIT>
+__global__ __launch_bounds__(64) void k_banded(BandedArgs A) {
+  __shared__ uint32_t ring[kBandedLdsWords];
+  const uint32_t t = blockIdx.x;
+  const uint32_t ra = A.pairs[2 * (uint64_t)t], rb = A.pairs[2 * (uint64_t)t + 1];
+  const uint32_t pa = A.seeds[2 * (uint64_t)t], pb = A.seeds[2 * (uint64_t)t + 1];
+  const int32_t w = A.w ? A.w[t] : A.w_scalar;
+  int32_t st = XD_TASK_OK;
+  if (ra >= A.st.n_reads || rb >= A.st.n_reads) {
+    st = XD_TASK_BAD_READ;
+  } else if ((uint64_t)pa + (uint64_t)A.k > A.st.len[ra] ||
+             (uint64_t)pb + (uint64_t)A.k > A.st.len[rb]) {
+    st = XD_TASK_BAD_SEED;
+  } else if (w < 0 || w > xd::kBandedMaxW) {
+    st = XD_TASK_BAD_X;
+  }
+  if (__builtin_amdgcn_readfirstlane(st) != XD_TASK_OK) {
+    if (xd::lane_id() == 0) {
+      A.score[t] = INT32_MIN;
+      A.end[2 * (uint64_t)t] = 0;
+      A.end[2 * (uint64_t)t + 1] = 0;
+      A.status[t] = st;
+      if (A.cells) A.cells[t] = 0;
+    }
+    return;
+  }
+  xd::BandTask bt;
+  bt.wa = A.st.words + A.st.word_off[__builtin_amdgcn_readfirstlane(ra)];
+  bt.wb = A.st.words + A.st.word_off[__builtin_amdgcn_readfirstlane(rb)];
+  bt.la = (int32_t)A.st.len[ra];
+  bt.lb = (int32_t)A.st.len[rb];
+  bt.c = (int32_t)pa - (int32_t)pb;
+  bt.w = w;
+  ExtOut o;
+  xd::banded_sw<UNIT>(bt, A.sc, ring, o);
+  if (xd::lane_id() == 0) {
+    A.score[t] = o.best;
+    A.end[2 * (uint64_t)t] = (uint32_t)o.bi;
+    A.end[2 * (uint64_t)t + 1] = (uint32_t)o.bj;
+    A.status[t] = XD_TASK_OK;
+    if (A.cells) A.cells[t] = o.cells;
+  }
 }
 
 // ---- launch sequences -------------------------------------------------------
@@ -1114,6 +1179,42 @@ int xd_align_pairs(const xd_store* store, uint64_t n_pairs, const uint32_t* pair
   hipError_t fe = hipFreeAsync(mem, stream);
   if (rc2) return rc2;
   if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
+  hipError_t le = hipGetLastError();
+  if (le != hipSuccess) return hip_fail(le, "kernel launch");
+  return XD_OK;
+}
+
+int xd_banded_batch(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,
+                    const int32_t* w, int32_t w_scalar, uint64_t n, int32_t k, int32_t match,
+                    int32_t mismatch, int32_t gap, int32_t* score, uint32_t* end,
+                    int32_t* status, uint64_t* cells, void* hip_stream) {
+  if (!store) return fail(XD_EINVAL, "xd_banded_batch: store is null");
+  int rc = check_scoring(k, match, mismatch, gap);
+  if (rc) return rc;
+  if (!w && (w_scalar < 0 || w_scalar > XD_BAND_MAX))
+    return fail(XD_EINVAL, "w_scalar must be in [0, %d] (got %d)", XD_BAND_MAX, w_scalar);
+  if (n > (1ull << 30)) return fail(XD_EINVAL, "n = %llu exceeds 2^30", (unsigned long long)n);
+  if (n && (!pairs || !seeds || !score || !end || !status))
+    return fail(XD_EINVAL, "xd_banded_batch: null task or result array");
+  if (n == 0) return XD_OK;
+  BandedArgs A;
+  A.st = {store->words, store->word_off, store->len, store->n_reads};
+  A.pairs = pairs;
+  A.seeds = seeds;
+  A.w = w;
+  A.w_scalar = w_scalar;
+  A.n = (uint32_t)n;
+  A.k = k;
+  A.sc = {match, mismatch, gap};
+  A.score = score;
+  A.end = end;
+  A.status = status;
+  A.cells = cells;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  if (match == 1)
+    hipLaunchKernelGGL(k_banded<true>, dim3((uint32_t)n), dim3(64), 0, stream, A);
+  else
+    hipLaunchKernelGGL(k_banded<false>, dim3((uint32_t)n), dim3(64), 0, stream, A);
   hipError_t le = hipGetLastError();
   if (le != hipSuccess) return hip_fail(le, "kernel launch");
   return XD_OK;

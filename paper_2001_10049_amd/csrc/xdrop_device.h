@@ -795,4 +795,215 @@ __device__ __forceinline__ void extend_band(const Ext& e, const Scoring& sc,
   res.cells = cells;
 }
 
+// ---- banded Smith-Waterman ----------------------------------------------
+//
+// Local alignment with linear gaps of a[1..la] (read A) against b[1..lb]
+// (read B), restricted to the cells within w of one diagonal, i - j = c
+// (paper section 2 names such banded searches beside X-drop):
+//   H(i,j) = max(0, H(i-1,j-1) + s(a_i,b_j), H(i-1,j) + gap, H(i,j-1) + gap)
+// inside the band, with zero boundary row and column, and neighbours outside
+// the band contributing nothing.  best = the largest H, first reached (smallest
+// i + j, then smallest i); cells = the band cells inside the grid.
+//
+// One wavefront sweeps the antidiagonals that hold band cells.  Scores use the
+// X-drop kernel's representation U = H + g*d + bias with dead cells 0, so the
+// floor H = 0 is the per-antidiagonal scalar g*d + bias; a diagonal neighbour
+// on the boundary row or column is not stored and is read as that floor.  The
+// band's rows on antidiagonal d are [ceil((d+c-w)/2), floor((d+c+w)/2)] (cut
+// to the grid), at most w+1 rows rising half a row per step, so each group of
+// GS steps places the 64-row window at the group's lowest row minus one (the
+// neighbour row) with one ds_bpermute slide.  Away from the grid's edges the
+// band's lane mask two steps on is the mask shifted up one lane, so a step
+// costs one scalar shift and one select for the band; near the edges the mask
+// is rebuilt each step from the grid limits.
+
+constexpr int kBandedMaxW = 48;  // 64 rows >= w + 2 + GS/2
+
+struct BandTask {
+  const uint32_t* wa;  // first word of read A
+  const uint32_t* wb;  // first word of read B
+  int32_t la, lb;      // read lengths
+  int32_t c, w;        // band: |i - j - c| <= w
+};
+
+// bits lo..hi of a 64-bit lane mask (empty when hi < lo; lo, hi clamped)
+__device__ __forceinline__ uint64_t lane_range(int32_t lo, int32_t hi) {
+  lo = max(lo, 0);
+  hi = min(hi, 63);
+  if (hi < lo) return 0ull;
+  const uint64_t top = hi == 63 ? ~0ull : ((2ull << hi) - 1ull);
+  return top & ~((1ull << lo) - 1ull);
+}
+
+template <bool UNIT>
+__device__ __forceinline__ void banded_sw(const BandTask& e, const Scoring& sc,
+                                          uint32_t* __restrict__ ring, ExtOut& res) {
+  constexpr int GS = 16;
+  constexpr int RING = 256, MASK = RING - 1, MIR = GS + 1, RA = 128;
+  const int lane = lane_id();
+  const int32_t g = __builtin_amdgcn_readfirstlane(-sc.G);
+  const int32_t C = __builtin_amdgcn_readfirstlane(sc.MM + 2 * g);
+  const uint32_t dM = __builtin_amdgcn_readfirstlane((uint32_t)(sc.M - sc.MM));
+  const int32_t la = __builtin_amdgcn_readfirstlane(e.la);
+  const int32_t lb = __builtin_amdgcn_readfirstlane(e.lb);
+  const int32_t c = __builtin_amdgcn_readfirstlane(e.c);
+  const int32_t w = __builtin_amdgcn_readfirstlane(e.w);
+  const int32_t bias = kBias0;
+  // band diagonals that meet the grid, and the cells on them
+  const int32_t dlo = max(c - w, 1 - lb);
+  const int32_t dhi = (la > 0 && lb > 0) ? min(c + w, la - 1) : dlo - 1;
+  uint32_t cnt = 0;
+  for (int32_t dl = dlo + lane; dl <= dhi; dl += 64)
+    cnt += (uint32_t)(min(la, lb + dl) - max(1, 1 + dl) + 1);
+  res.cells = wave_sum_u64(cnt);
+  res.best = 0;
+  res.bi = 0;
+  res.bj = 0;
+  res.flags = kExtDone;
+  if (dlo > dhi) return;
+  // first and last antidiagonal with band cells: diagonal delta starts at
+  // i + j = 2 + |delta| and ends at min(la, lb+delta) + min(lb, la-delta)
+  const int32_t d_first = 2 + (dlo > 0 ? dlo : (dhi < 0 ? -dhi : 0));
+  const int32_t dpk = min(max(la - lb, dlo), dhi);
+  const int32_t d_last = dpk <= la - lb ? 2 * lb + dpk : 2 * la - dpk;
+  // band rows on antidiagonal dd, inside the grid
+  auto row_lo = [&](int32_t dd) { return max(max(1, dd - lb), (dd + c - w + 1) >> 1); };
+  auto row_hi = [&](int32_t dd) { return min(min(la, dd - 1), (dd + c + w) >> 1); };
+
+  int32_t base = row_lo(d_first) - 1;  // row of lane 0
+  int32_t U1 = 0, Up = 0;  // U on the last antidiagonal, and on the one before shifted up a row
+  uint32_t aa = 0;
+  uint8_t* aring = (uint8_t*)(ring + RING + MIR);
+  auto word_of = [&](const uint32_t* wd, int32_t q, int32_t lim) -> uint32_t {
+    uint32_t v = 0;
+    if (q >= 1 & q <= lim) v = wd[(q - 1) >> 4];
+    return v;
+  };
+  auto code_in = [&](uint32_t wd, int32_t q) -> uint32_t {
+    return (wd >> (((q - 1) & 15) << 1)) & 3u;
+  };
+  // b ring (one word per j, (match - mismatch) << 8*code), chunked by 64 j
+  int32_t filled = ((d_first - base - 64) & ~63) - 1;  // highest j held
+  filled = max(filled, -1);
+  uint32_t pf_b = word_of(e.wb, filled + 1 + lane, lb);
+  auto fill_to = [&](int32_t jhi) {
+    while (filled < jhi) {
+      const int32_t j = filled + 1 + lane;
+      const uint32_t v = (j >= 1 & j <= lb) ? (dM << (8u * code_in(pf_b, j))) : 0u;
+      const int slot = j & MASK;
+      ring[slot] = v;
+      if (slot < MIR) ring[RING + slot] = v;
+      pf_b = word_of(e.wb, j + 64, lb);
+      filled += 64;
+    }
+    wave_lds_fence();
+  };
+  // a ring (one byte per row), chunked by 64 rows
+  int32_t filled_a = (max(base, 0) & ~63) - 1;
+  uint32_t pf_a = word_of(e.wa, filled_a + 1 + lane, la);
+  auto load_a = [&]() {
+    while (filled_a < base + 63) {
+      const int32_t i = filled_a + 1 + lane;
+      aring[i & (RA - 1)] = (uint8_t)((i >= 1 & i <= la) ? code_in(pf_a, i) : 0u);
+      pf_a = word_of(e.wa, i + 64, la);
+      filled_a += 64;
+    }
+    wave_lds_fence();
+    aa = aring[(base + lane) & (RA - 1)];
+  };
+  load_a();
+
+  int32_t d = d_first;                 // next antidiagonal
+  int32_t thr = g * d + bias;          // T + g*d + bias: an improving cell exceeds it
+  int32_t bi = 0, dstar = 0;
+  while (d <= d_last) {
+    // slide the window to the group's lowest band row minus one
+    const int32_t nb = row_lo(d) - 1;
+    if (nb > base) {
+      const int32_t sl = nb - base;
+      const int src = lane + sl;
+      const bool inside = src < 64;
+      const int32_t u1 = __builtin_amdgcn_ds_bpermute((src & 63) << 2, U1);
+      const int32_t up = __builtin_amdgcn_ds_bpermute((src & 63) << 2, Up);
+      U1 = inside ? u1 : 0;
+      Up = inside ? up : 0;
+      base = nb;
+      load_a();
+    }
+    fill_to(d + GS - 1 - base);
+    const int32_t d1 = d + GS - 1;
+    // away from the grid's edges the band masks just shift up every two steps
+    const bool interior = ((d + c - w + 1) >> 1) >= 1 && ((d1 + c - w + 1) >> 1) >= d1 - lb &&
+                          ((d1 + c + w) >> 1) <= la && ((d + c + w) >> 1) <= d - 1;
+    uint64_t mk[2];
+    mk[0] = lane_range(row_lo(d) - base, row_hi(d) - base);
+    mk[1] = lane_range(row_lo(d + 1) - base, row_hi(d + 1) - base);
+    const int32_t r = (d - base - lane) & MASK;
+    const uint8_t* rbytes = (const uint8_t*)ring;
+    const uint32_t ad = ((uint32_t)r << 2) + aa;
+    uint32_t bmv[GS];
+#pragma unroll
+    for (int t = 0; t < GS; ++t) bmv[t] = rbytes[ad + 4 * t];
+    uint64_t imp[GS][1];
+    uint64_t last = 0;
+    int32_t lastt = 0;
+    const int32_t thr0 = thr;
+    int32_t fl2 = g * (d - 2) + bias;  // floor two antidiagonals back
+    int32_t fl1 = fl2 + g;
+    auto body = [&](auto t_tag) {
+      constexpr int t = decltype(t_tag)::value;
+      const int32_t fl = fl1 + g;  // floor of this antidiagonal
+      uint64_t m;
+      if (interior) {
+        m = mk[t & 1];
+        mk[t & 1] = m << 1;
+      } else {
+        m = lane_range(row_lo(d + t) - base, row_hi(d + t) - base);
+      }
+      const int32_t upv = shr1_zero(U1);
+      const int32_t dg = max(Up, fl2);
+      int32_t s = max(max(dg + (int32_t)bmv[t] + C, upv), U1);
+      s = max(s, fl);
+      const bool in = __builtin_amdgcn_inverse_ballot_w64(m);
+      const int32_t u = in ? s : 0;
+      const uint64_t im = ballot64(u > thr);
+      Up = upv;
+      U1 = u;
+      if constexpr (UNIT) {
+        imp[t][0] = im;
+        thr = add_nonzero(thr, g, im);
+      } else {
+        int32_t dT = 0;
+        if (im) {
+          const int32_t vmax = __builtin_amdgcn_readfirstlane(wave_max_i32(u));
+          dT = vmax - thr;
+          last = ballot64(u == vmax);
+          lastt = t + 1;
+        }
+        thr += g + dT;
+      }
+      fl2 = fl1;
+      fl1 = fl;
+    };
+    static_for<GS>(body);
+    if constexpr (UNIT) {
+      if (thr != thr0 + GS * g) {
+        uint64_t lm[1];
+        int32_t kk = 0;
+        last_nonzero<GS - 1, GS, 1>(imp, lm, kk);
+        bi = base + sctz64(lm[0]);
+        dstar = d + kk - 1;
+      }
+    } else if (lastt) {
+      bi = base + (int32_t)__builtin_ctzll(last);
+      dstar = d + lastt - 1;
+    }
+    d += GS;
+  }
+  // thr = T + g*d + bias with d the next antidiagonal
+  res.best = thr - g * d - bias;
+  res.bi = res.best > 0 ? bi : 0;
+  res.bj = res.best > 0 ? dstar - bi : 0;
+}
+
 }  // namespace xd
