@@ -32,3 +32,21 @@ def result_digests(res, chunk=CHUNK):
             h.update(np.ascontiguousarray(a).tobytes())
         out.append(h.hexdigest()[:24])
     return out
+
+
+def reads_digest(w) -> str:
+    """Digest of a workload's read set alone (bases and lengths)."""
+    h = hashlib.sha256()
+    for a in (w.codes, w.length):
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()[:32]
+
+
+def overlap_digest(pairs, seed_off, seeds) -> str:
+    """Digest of a candidate-pair result: pairs uint32[P, 2], seed_off
+    uint64[P + 1], seeds uint32[S, 2] (any integer dtypes of those widths)."""
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(pairs).view(np.uint32).tobytes())
+    h.update(np.ascontiguousarray(seed_off).view(np.uint64).tobytes())
+    h.update(np.ascontiguousarray(seeds).view(np.uint32).tobytes())
+    return h.hexdigest()[:32]

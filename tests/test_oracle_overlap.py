@@ -20,7 +20,8 @@ def test_hand_case():
     # AAA: (0,0) (1,1); AAC: (0,1) (1,2); CAA only in read 1; GGG twice in read 2
     assert pairs.tolist() == [[0, 1]]
     assert seeds.tolist() == [[0, 1], [1, 2]] and so.tolist() == [0, 2]
-    assert st == dict(kmers=2 + 3 + 2, distinct=4, retained=3, occurrences=6)
+    assert st == dict(kmers=2 + 3 + 2, distinct=4, retained=3, occurrences=6,
+                    non_singletons=3)
     # GGG occurs twice but only within read 2: retained, yet no pair; with
     # count_hi = 1 nothing is retained
     assert ov.find_overlaps(codes, off, length, 3, 2, 1)[0].size == 0
@@ -69,3 +70,29 @@ def test_planted_overlap():
     assert set(range(500, 1500 - 17 + 1)) <= diag
     for pa, pb in seeds.tolist():
         assert np.array_equal(A[pa:pa + 17], B[pb:pb + 17])
+
+
+def test_sorted_variant_matches():
+    # the sort-based form (for large read sets) equals the dict form,
+    # statistics included, with repeats, short reads and several bounds
+    rng = np.random.default_rng(9)
+    for trial in range(10):
+        base = rand_codes(rng, 3000)
+        seqs = []
+        for _ in range(int(rng.integers(1, 30))):
+            n = int(rng.integers(0, 400))
+            s = int(rng.integers(0, 3000 - n + 1))
+            r = base[s:s + n].copy()
+            flip = rng.random(n) < 0.05
+            r[flip] = rng.integers(0, 4, int(flip.sum()))
+            seqs.append(r.astype(np.uint8))
+        if trial % 3 == 0:
+            seqs.append(np.zeros(100, np.uint8))          # homopolymer: one k-mer, many times
+        codes, off, length = _reads(*seqs)
+        k = int(rng.choice([5, 11, 17, 31]))
+        lo, hi = 2, int(rng.integers(1, 12))
+        a = ov.find_overlaps(codes, off, length, k, lo, hi)
+        b = ov.find_overlaps_sorted(codes, off, length, k, lo, hi)
+        for x, y in zip(a[:3], b[:3]):
+            assert x.dtype == y.dtype and np.array_equal(x, y), trial
+        assert a[3] == b[3], trial
