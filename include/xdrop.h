@@ -219,6 +219,52 @@ int xd_banded_batch(const xd_store* store, const uint32_t* pairs, const uint32_t
                     int32_t mismatch, int32_t gap, int32_t* score, uint32_t* end,
                     int32_t* status, uint64_t* cells, void* hip_stream);
 
+/* ---- candidate pairs from shared k-mers ------------------------------------ */
+
+#define XD_OVERLAP_K_MAX 31 /* longest k-mer */
+#define XD_OVERLAP_M_MAX 64 /* largest frequency bound m */
+
+typedef struct {
+  uint64_t kmers;          /* k-mer occurrences in the reads (forward strand) */
+  uint64_t bloom_repeats;  /* occurrences the first filter had seen before (diagnostic) */
+  uint64_t table_keys;     /* distinct k-mers inserted in the hash table (diagnostic) */
+  uint64_t table_slots;    /* hash table capacity used (diagnostic) */
+  uint64_t non_singletons; /* distinct k-mers occurring at least twice */
+  uint64_t retained;       /* distinct k-mers occurring 2..m times */
+  uint64_t occurrences;    /* occurrences of retained k-mers */
+  uint64_t seeds;          /* (pair, seed) tasks in the output */
+  uint64_t pairs;          /* distinct read pairs in the output */
+} xd_overlap_counts;
+
+/* Candidate read pairs (paper section 4 stages 1-3; sections 6-8): the reads
+ * of the store are cut into their k-mers (every start p with p + k <= length,
+ * forward strand); a k-mer occurring 2..m times over all reads is retained
+ * (singletons and k-mers above the frequency bound m are dropped, section 3),
+ * and every two occurrences of a retained k-mer in different reads ra < rb,
+ * at pa in ra and pb in rb, form the seed (pa, pb) of the pair (ra, rb)
+ * (Alg. 1).  Output, device pointers, caller-owned:
+ *   pairs    uint32[2 max_pairs]      (ra, rb), sorted, distinct, ra < rb
+ *   seed_off uint64[max_pairs + 1]    pair q's seeds are entries
+ *                                     [seed_off[q], seed_off[q+1]) of seeds
+ *   seeds    uint32[2 max_seeds]      (pa, pb), increasing within each pair
+ * of which the first P pairs, P + 1 offsets and S seeds are written
+ * which is the input xd_align_pairs takes (rc = NULL).  P and S go to
+ * counts->pairs and counts->seeds.  With pairs, seed_off and seeds all NULL
+ * only the counts are computed; when P > max_pairs or S > max_seeds nothing is
+ * written and XD_EAGAIN is returned with the counts filled in.  The result is
+ * deterministic.  1 <= k <= XD_OVERLAP_K_MAX, 1 <= m <= XD_OVERLAP_M_MAX;
+ * bloom_bits = bits of the first filter per k-mer occurrence (0 = 16, else
+ * 4..64; a speed/memory setting that does not change the result).  Device
+ * scratch is taken from the stream's memory pool: about bloom_bits/8 bytes
+ * per k-mer for the filter plus (12 + 8 m) bytes per hash-table slot, the
+ * table sized at twice the repeated occurrences.  Runs on hip_stream and
+ * returns when done (the counts need host round trips).  More than 2^32 - 2
+ * k-mers or seeds -> XD_EINVAL. */
+int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, uint32_t bloom_bits,
+                     uint64_t max_pairs, uint32_t* pairs, uint64_t* seed_off,
+                     uint64_t max_seeds, uint32_t* seeds, xd_overlap_counts* counts,
+                     void* hip_stream);
+
 /* A captured batch: the batched form's kernels recorded once in a hipGraph
  * for fixed buffers (same meaning as xd_align_batch's) and replayed by
  * xd_plan_launch.  The plan owns its scratch memory.  Between launches the

@@ -14,12 +14,14 @@ X_MAX = 1 << 20
 BAND_MAX = 48
 SCORE_LIMIT = 127
 READ_MAX = 1 << 22
+OVERLAP_K_MAX = 31
+OVERLAP_M_MAX = 64
 
 # every symbol include/xdrop.h declares
 EXPORTS = (
     "xd_pack_reads", "xd_store_create", "xd_store_create_from_codes", "xd_store_destroy",
     "xd_store_info", "xd_align_batch", "xd_align_batch_persistent", "xd_align_pairs",
-    "xd_banded_batch",
+    "xd_banded_batch", "xd_find_overlaps",
     "xd_plan_create",
     "xd_plan_launch", "xd_plan_destroy", "xd_profile_enable", "xd_profile_read",
     "xd_server_request_bytes", "xd_server_fixed_bytes", "xd_server_create", "xd_server_submit", "xd_server_poll",
@@ -55,6 +57,12 @@ class ServerCounters(ctypes.Structure):
                 ("pending", ctypes.c_uint64), ("inflight_bytes", ctypes.c_uint64)]
 
 
+class OverlapCounts(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in (
+        "kmers", "bloom_repeats", "table_keys", "table_slots", "non_singletons", "retained",
+        "occurrences", "seeds", "pairs")]
+
+
 class Profile(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_uint64), ("extensions", ctypes.c_uint64),
                 ("to_tier2", ctypes.c_uint64), ("to_tier3", ctypes.c_uint64),
@@ -81,6 +89,13 @@ def load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError("libxdrop.so is not built (run __graft_entry__.build() or "
                           "python -m paper_2001_10049_amd.build)")
+    try:
+        # torch's HIP runtime is loaded first so that the library binds to the
+        # same instance; a process whose first HIP runtime came in with the
+        # library found no GPU through torch afterwards
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
     lib.xd_pack_reads.argtypes = [vp, vp, vp, u32, vp, vp, ctypes.POINTER(u64)]
@@ -107,6 +122,9 @@ def load() -> ctypes.CDLL:
     lib.xd_banded_batch.argtypes = [vp, vp, vp, vp, i32, u64, i32, i32, i32, i32, vp, vp, vp,
                                     vp, vp]
     lib.xd_banded_batch.restype = ctypes.c_int
+    lib.xd_find_overlaps.argtypes = [vp, i32, u32, u32, u64, vp, vp, u64, vp,
+                                     ctypes.POINTER(OverlapCounts), vp]
+    lib.xd_find_overlaps.restype = ctypes.c_int
     lib.xd_plan_create.argtypes = batch + [ctypes.POINTER(Tuning), ctypes.POINTER(vp)]
     lib.xd_plan_create.restype = ctypes.c_int
     lib.xd_plan_launch.argtypes = [vp, vp]

@@ -33,6 +33,7 @@
 #include <vector>
 
 #include "xdrop.h"
+#include "store_view.h"
 #include "xdrop_device.h"
 
 using xd::ExtOut;
@@ -840,6 +841,7 @@ struct xd_store {
   uint32_t n_reads = 0;
   uint32_t max_len = 0;
   int device = 0;
+  std::vector<uint32_t> host_len;
 };
 
 struct xd_plan {
@@ -946,6 +948,19 @@ __attribute__((visibility("hidden"))) int xd_internal_fail(int code, const char*
   return code;
 }
 
+__attribute__((visibility("hidden"))) int xd_internal_store_view(const xd_store* s,
+                                                                 StoreView* v) {
+  if (!s) return fail(XD_EINVAL, "store is null");
+  v->words = s->words;
+  v->word_off = s->word_off;
+  v->len = s->len;
+  v->host_len = s->host_len.data();
+  v->n_reads = s->n_reads;
+  v->max_len = s->max_len;
+  v->device = s->device;
+  return XD_OK;
+}
+
 // device bytes of the band tier's rows for a store whose longest read has
 // max_len bases, with `blocks` workgroups (0 = the default count)
 __attribute__((visibility("hidden"))) uint64_t xd_internal_band_bytes(uint32_t max_len,
@@ -1009,6 +1024,7 @@ int xd_store_create(const uint32_t* words, uint64_t n_words, const uint64_t* wor
   s->n_words = n_words;
   s->n_reads = n_reads;
   s->max_len = max_len;
+  s->host_len.assign(len, len + n_reads);
   hipError_t e = hipGetDevice(&s->device);
   const uint64_t wb = (n_words ? n_words : 1) * sizeof(uint32_t);
   if (e == hipSuccess) e = hipMalloc((void**)&s->words, wb);

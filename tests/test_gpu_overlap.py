@@ -1,0 +1,151 @@
+"""Candidate pairs on the GPU (xd_find_overlaps) against the oracle: small
+read sets element by element over k, m and filter sizes; the c2-small read
+set exactly; the full c2 read set (138 Mbp) by the digest of the oracle's
+whole result recorded by tests/golden/make_overlap_digests.py."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import overlap as ov
+from oracle import pairs as opairs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+from digest import overlap_digest, reads_digest  # noqa: E402
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2001_10049_amd as xd  # noqa: E402
+
+RECORD = json.load(open(os.path.join(HERE, "golden", "overlap_digests.json")))
+EXACT = ("kmers", "non_singletons", "retained", "occurrences")
+
+
+def _reads(seqs):
+    length = np.array([len(s) for s in seqs], np.uint32)
+    off = np.concatenate([[0], np.cumsum(length)[:-1]]).astype(np.uint64) if seqs else \
+        np.zeros(0, np.uint64)
+    codes = np.concatenate(seqs).astype(np.uint8) if seqs else np.zeros(0, np.uint8)
+    return codes, off, length
+
+
+def gpu(codes, off, length, k, m, bloom_bits=0, capacity=None):
+    with xd.ReadStore(codes, off, length) as st:
+        r = xd.find_overlaps(st, k=k, m=m, bloom_bits=bloom_bits, capacity=capacity)
+    torch.cuda.synchronize()
+    return (r["pairs"].cpu().numpy().view(np.uint32).reshape(-1, 2),
+            r["seed_off"].cpu().numpy().view(np.uint64),
+            r["seeds"].cpu().numpy().view(np.uint32).reshape(-1, 2), r["counts"])
+
+
+def assert_same(got, ref, label):
+    for name, g, o in zip(("pairs", "seed_off", "seeds"), got[:3], ref[:3]):
+        assert g.shape == o.shape and np.array_equal(g, o), "%s: %s differ" % (label, name)
+    for f in EXACT:
+        assert got[3][f] == ref[3][f], "%s: %s %d != %d" % (label, f, got[3][f], ref[3][f])
+    assert got[3]["pairs"] == ref[0].shape[0] and got[3]["seeds"] == ref[2].shape[0]
+
+
+def test_small_sets_match_oracle():
+    rng = np.random.default_rng(21)
+    for trial in range(40):
+        base = rng.integers(0, 4, 4000).astype(np.uint8)
+        seqs = []
+        for _ in range(int(rng.integers(1, 40))):
+            n = int(rng.integers(0, 700))
+            s = int(rng.integers(0, 4000 - n + 1))
+            r = base[s:s + n].copy()
+            flip = rng.random(n) < 0.04
+            r[flip] = rng.integers(0, 4, int(flip.sum()))
+            seqs.append(r)
+        if trial % 4 == 0:
+            seqs.append(np.full(300, 2, np.uint8))   # one k-mer, far above m
+        if trial % 5 == 1:
+            seqs.append(np.tile(np.array([0, 1], np.uint8), 50))
+        k = int(rng.choice([1, 2, 5, 11, 17, 31]))
+        m = int(rng.choice([1, 2, 3, 8, 64]))
+        codes, off, length = _reads(seqs)
+        ref = ov.find_overlaps(codes, off, length, k, 2, m)
+        got = gpu(codes, off, length, k, m)
+        assert_same(got, ref, "trial %d (k=%d, m=%d, %d reads)" % (trial, k, m, len(seqs)))
+
+
+def test_degenerate_inputs():
+    for seqs in ([], [np.zeros(0, np.uint8)], [np.arange(10, dtype=np.uint8) % 4] * 3,
+                 [np.zeros(16, np.uint8), np.zeros(16, np.uint8)]):
+        codes, off, length = _reads(seqs)
+        ref = ov.find_overlaps(codes, off, length, 17, 2, 8)
+        got = gpu(codes, off, length, 17, 8)
+        assert_same(got, ref, "%d reads" % len(seqs))
+        assert got[1].tolist() == ref[1].tolist()
+
+
+def test_c2_small_exact_and_filter_sizes():
+    w = synth.config("c2-small")
+    ref = ov.find_overlaps_sorted(w.codes, w.off, w.length, 17, 2, 8)
+    rec = RECORD["c2-small"]
+    assert reads_digest(w) == rec["reads"]
+    assert overlap_digest(*ref[:3]) == rec["digest"]
+    for bits in (4, 16, 64):  # the first filter's size changes speed, not the result
+        got = gpu(w.codes, w.off, w.length, 17, 8, bloom_bits=bits)
+        assert_same(got, ref, "c2-small bloom_bits=%d" % bits)
+
+
+def test_capacity_and_eagain():
+    w = synth.config("c2-small")
+    with xd.ReadStore.from_workload(w) as st:
+        r = xd.find_overlaps(st, k=17, m=8)
+        P, S = r["counts"]["pairs"], r["counts"]["seeds"]
+        with pytest.raises(xd.XdropError) as e:
+            xd.find_overlaps(st, k=17, m=8, capacity=(P - 1, S))
+        assert e.value.code == xd._lib.XD_EAGAIN
+        with pytest.raises(xd.XdropError):
+            xd.find_overlaps(st, k=32, m=8)
+        with pytest.raises(xd.XdropError):
+            xd.find_overlaps(st, k=17, m=65)
+        again = xd.find_overlaps(st, k=17, m=8, capacity=(P, S))
+        for f in ("pairs", "seed_off", "seeds"):
+            assert torch.equal(r[f], again[f])
+
+
+def test_c2_full_read_set_matches_record():
+    w = synth.config("c2")
+    rec = RECORD["c2"]
+    assert reads_digest(w) == rec["reads"]
+    got = gpu(w.codes, w.off, w.length, rec["k"], rec["m"])
+    for f in EXACT + ("pairs", "seeds"):
+        assert got[3][f] == rec[f], "c2: %s %d != %d" % (f, got[3][f], rec[f])
+    assert overlap_digest(*got[:3]) == rec["digest"]
+
+
+def test_pairs_feed_alignment():
+    # the candidate lists go straight into xd_align_pairs (one seed and all
+    # seeds k apart); a sample of pairs is checked against the oracle
+    w = synth.config("c2-small")
+    with xd.ReadStore.from_workload(w) as st:
+        r = xd.find_overlaps(st, k=17, m=8)
+        P = r["counts"]["pairs"]
+        idx = np.linspace(0, P - 1, 40).astype(np.int64)
+        so = r["seed_off"].cpu().numpy()
+        pairs_h = r["pairs"].cpu().numpy()
+        seeds_h = r["seeds"].cpu().numpy()
+        for max_seeds, min_dist in ((1, 17), (0, 17)):
+            out = xd.align_pairs(st, r["pairs"], r["seed_off"], r["seeds"], x_scalar=25,
+                                 min_dist=min_dist, max_seeds=max_seeds, k=17)
+            torch.cuda.synchronize()
+            sub_off = np.concatenate([[0], np.cumsum(so[idx + 1] - so[idx])]).astype(np.uint64)
+            sub_seeds = np.concatenate([seeds_h[so[i]:so[i + 1]] for i in idx])
+            ref = opairs.align_pairs(w.codes, w.off, w.length, pairs_h[idx], sub_off, sub_seeds,
+                                     x_scalar=25, min_dist=min_dist, max_seeds=max_seeds, k=17)
+            for f in ("score", "status", "seed_idx", "n_kept"):
+                assert np.array_equal(out[f].cpu().numpy()[idx], ref[f]), (max_seeds, f)
+            assert np.array_equal(out["cells"].cpu().numpy()[idx].astype(np.uint64),
+                                  ref["cells"].astype(np.uint64))
