@@ -76,8 +76,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build_lib()
+        build_lib()  # compiles when missing or older than its sources
         lib = ctypes.CDLL(_LIB_PATH)
         vp = ctypes.c_void_p
         lib.xo_extend.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, ctypes.c_int32,
@@ -101,6 +100,11 @@ def _load():
                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_int32,
                                        ctypes.POINTER(_BandedTask)]
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.xo_banded_trace.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.POINTER(_Banded), i64p, i64p, vp,
+                                        ctypes.c_int64, i64p]
         _lib = lib
     return _lib
 
@@ -211,6 +215,54 @@ def banded(a, b, c, w, match=1, mismatch=-1, gap=-1):
                          ctypes.byref(r)):
         raise MemoryError("banded oracle failed")
     return int(r.best), int(r.i), int(r.j), int(r.cells)
+
+
+OP_M, OP_I, OP_D = 0, 1, 2  # run-length entries: length << 2 | op
+
+
+def banded_trace(a, b, c, w, match=1, mismatch=-1, gap=-1):
+    """Banded Smith-Waterman with traceback (banded_oracle.c) -> (best, i, j,
+    cells, beg_i, beg_j, ops uint32 array of run-length entries)."""
+    a, b = _u8(a), _u8(b)
+    pa = a if a.size else np.zeros(1, np.uint8)
+    pb = b if b.size else np.zeros(1, np.uint8)
+    r = _Banded()
+    bi, bj, nops = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    cap = a.size + b.size + 1
+    ops = np.zeros(cap, np.uint32)
+    if _load().xo_banded_trace(_p(pa), a.size, _p(pb), b.size, int(c), int(w), match, mismatch,
+                               gap, ctypes.byref(r), ctypes.byref(bi), ctypes.byref(bj), _p(ops),
+                               cap, ctypes.byref(nops)):
+        raise MemoryError("banded traceback oracle failed")
+    return (int(r.best), int(r.i), int(r.j), int(r.cells), int(bi.value), int(bj.value),
+            ops[:nops.value].copy())
+
+
+def banded_trace_batch(codes, off, length, pairs, seeds, w, k=17, match=1, mismatch=-1, gap=-1):
+    """Banded tasks with traceback -> dict(score, beg[n, 2], end[n, 2], cells,
+    status, ops = list of run-length arrays); statuses as banded_batch."""
+    base = banded_batch(codes, off, length, pairs, seeds, w, k, match, mismatch, gap)
+    codes = np.ascontiguousarray(codes, np.uint8)
+    pairs = np.asarray(pairs, np.uint32).reshape(-1, 2)
+    seeds = np.asarray(seeds, np.uint32).reshape(-1, 2)
+    n = pairs.shape[0]
+    ws = np.broadcast_to(np.asarray(w, np.int64), (n,))
+    base["beg"] = np.zeros((n, 2), np.uint32)
+    base["ops"] = []
+    for t in range(n):
+        if base["status"][t] != 0:
+            base["ops"].append(np.zeros(0, np.uint32))
+            continue
+        ra, rb = int(pairs[t, 0]), int(pairs[t, 1])
+        A = codes[int(off[ra]):int(off[ra]) + int(length[ra])]
+        B = codes[int(off[rb]):int(off[rb]) + int(length[rb])]
+        best, i, j, cells, bi, bj, ops = banded_trace(A, B, int(seeds[t, 0]) - int(seeds[t, 1]),
+                                                      int(ws[t]), match, mismatch, gap)
+        assert (best, i, j, cells) == (base["score"][t], base["end"][t][0], base["end"][t][1],
+                                       base["cells"][t])
+        base["beg"][t] = (bi, bj)
+        base["ops"].append(ops)
+    return base
 
 
 def banded_batch(codes, off, length, pairs, seeds, w, k=17, match=1, mismatch=-1, gap=-1):

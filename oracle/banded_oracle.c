@@ -111,3 +111,96 @@ int xo_banded_task(const uint8_t* codes, const uint64_t* off, const uint32_t* le
   out->status = XO_TASK_OK;
   return 0;
 }
+
+/*
+ * Traceback of the banded local alignment (a reading: the paper names banded
+ * Smith-Waterman but no alignment output, so the textbook traceback is used
+ * with a fixed rule for ties).  From the end cell (i*, j*) while H(i,j) > 0,
+ * step to the neighbour that produced H(i,j), preferring (i-1, j-1), then
+ * (i-1, j), then (i, j-1); the walk stops on the first cell with H = 0, the
+ * begin cell (i0, j0): the alignment covers a[i0+1..i*] and b[j0+1..j*].
+ * Steps: M = (i-1, j-1) (a_i against b_j), D = (i-1, j) (a_i against a gap),
+ * I = (i, j-1) (b_j against a gap).  ops[] is the run-length form from begin
+ * to end, entry = run length << 2 | op.  The full band of H is kept.
+ */
+int xo_banded_trace(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, int64_t c, int64_t w,
+                    int32_t match, int32_t mismatch, int32_t gap, xo_banded_result* out,
+                    int64_t* beg_i, int64_t* beg_j, uint32_t* ops, int64_t max_ops,
+                    int64_t* n_ops) {
+  const int64_t W = 2 * w + 1;
+  int64_t* H = (int64_t*)malloc(sizeof(int64_t) * (size_t)((m + 1) * W));
+  if (!H) return -1;
+  /* H(i, j) is H[i * W + (j - (i - c - w))] for band cells of row i */
+#define IN_BAND(i, j) ((j) - (i) + c + w >= 0 && (j) - (i) + c + w < W)
+#define CELL(i, j) H[(i) * W + ((j) - ((i) - c - w))]
+  /* is (i, j) a cell whose H is defined: row or column 0, or a band cell */
+#define DEFINED(i, j) ((i) >= 0 && (j) >= 0 && (i) <= m && (j) <= n && \
+                       ((i) == 0 || (j) == 0 || IN_BAND(i, j)))
+#define GET(i, j) (((i) == 0 || (j) == 0) ? 0 : CELL(i, j))
+  int64_t best = 0, bi = 0, bj = 0;
+  uint64_t cells = 0;
+  for (int64_t i = 1; i <= m; ++i)
+    for (int64_t j = i - c - w; j <= i - c + w; ++j) {
+      if (j < 1 || j > n) continue;
+      ++cells;
+      const int64_t s = (a[i - 1] == b[j - 1]) ? match : mismatch;
+      int64_t h = 0;
+      if (DEFINED(i - 1, j - 1) && GET(i - 1, j - 1) + s > h) h = GET(i - 1, j - 1) + s;
+      if (DEFINED(i - 1, j) && GET(i - 1, j) + gap > h) h = GET(i - 1, j) + gap;
+      if (DEFINED(i, j - 1) && GET(i, j - 1) + gap > h) h = GET(i, j - 1) + gap;
+      CELL(i, j) = h;
+      if (h > best || (h == best && h > 0 && (i + j < bi + bj || (i + j == bi + bj && i < bi)))) {
+        best = h;
+        bi = i;
+        bj = j;
+      }
+    }
+  out->best = best;
+  out->i = bi;
+  out->j = bj;
+  out->cells = cells;
+  /* walk back, collecting steps in reverse */
+  int64_t i = bi, j = bj, steps = 0;
+  uint8_t* rev = (uint8_t*)malloc((size_t)(m + n + 1));
+  if (!rev) {
+    free(H);
+    return -1;
+  }
+  while (i > 0 && j > 0 && GET(i, j) > 0) {
+    const int64_t h = GET(i, j);
+    const int64_t s = (a[i - 1] == b[j - 1]) ? match : mismatch;
+    if (DEFINED(i - 1, j - 1) && h == GET(i - 1, j - 1) + s) {
+      rev[steps++] = XO_OP_M;
+      --i;
+      --j;
+    } else if (DEFINED(i - 1, j) && h == GET(i - 1, j) + gap) {
+      rev[steps++] = XO_OP_D;
+      --i;
+    } else if (DEFINED(i, j - 1) && h == GET(i, j - 1) + gap) {
+      rev[steps++] = XO_OP_I;
+      --j;
+    } else {
+      free(rev);
+      free(H);
+      return -1; /* unreachable: H(i,j) > 0 comes from a neighbour */
+    }
+  }
+#undef GET
+#undef DEFINED
+#undef CELL
+#undef IN_BAND
+  *beg_i = best > 0 ? i : 0;
+  *beg_j = best > 0 ? j : 0;
+  int64_t k = 0;
+  for (int64_t t = steps - 1; t >= 0;) {
+    int64_t u = t;
+    while (u >= 0 && rev[u] == rev[t]) --u;
+    if (k < max_ops) ops[k] = (uint32_t)(((t - u) << 2) | rev[t]);
+    ++k;
+    t = u;
+  }
+  *n_ops = k;
+  free(rev);
+  free(H);
+  return 0;
+}

@@ -86,6 +86,18 @@ typedef struct {
 int xo_banded(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, int64_t c, int64_t w,
               int32_t match, int32_t mismatch, int32_t gap, xo_banded_result* out);
 
+/* Traceback of the banded alignment (banded_oracle.c): ops, run-length
+   entries (length << 2 | op) from begin to end; *n_ops may exceed max_ops
+   (entries past max_ops are not written).  Returns 0, or -1 when out of
+   memory. */
+#define XO_OP_M 0 /* a_i against b_j */
+#define XO_OP_I 1 /* b_j against a gap */
+#define XO_OP_D 2 /* a_i against a gap */
+int xo_banded_trace(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, int64_t c, int64_t w,
+                    int32_t match, int32_t mismatch, int32_t gap, xo_banded_result* out,
+                    int64_t* beg_i, int64_t* beg_j, uint32_t* ops, int64_t max_ops,
+                    int64_t* n_ops);
+
 /* One banded task: reads ra, rb of the read set, band around the diagonal of
    the seed (pa, pb) (c = pa - pb).  Returns 0, or -1 on bad scoring or out of
    memory. */
