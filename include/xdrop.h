@@ -62,6 +62,10 @@ extern "C" {
 #define XD_TASK_BAND_OVERFLOW 4 /* reserved: no longer produced (bands wider than the
                                    1024-cell window run in the band tier) */
 #define XD_TASK_NO_SEED 5  /* xd_align_pairs: the pair's seed list is empty */
+#define XD_TASK_OPS_OVERFLOW 6 /* xd_banded_traceback: the alignment needs more than
+                                  max_ops run-length entries (n_ops holds the count) */
+#define XD_TASK_TRACE_FAULT 7  /* xd_banded_traceback: internal inconsistency, not
+                                  expected (the walk left the stored band) */
 
 /* limits (checked; violations return XD_EINVAL) */
 #define XD_X_MAX (1 << 20)           /* largest X */
@@ -264,6 +268,34 @@ int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, uint32_t bloo
                      uint64_t max_pairs, uint32_t* pairs, uint64_t* seed_off,
                      uint64_t max_seeds, uint32_t* seeds, xd_overlap_counts* counts,
                      void* hip_stream);
+
+/* Banded Smith-Waterman with the alignment itself: xd_banded_batch's
+ * score, end, status and cells, plus the begin cell and the alignment path by
+ * the textbook traceback (a reading; the paper gives no alignment output):
+ * from the end cell, while H(i,j) > 0, step to the neighbour that produced
+ * H(i,j), preferring (i-1, j-1), then (i-1, j), then (i, j-1); the walk ends
+ * on the first cell (i0, j0) with H = 0.
+ *   beg    uint32[2n]  (i0, j0): the alignment covers A[i0, i*) and B[j0, j*)
+ *                      (0-based, half-open; (0, 0) when score is 0)
+ *   ops    uint32[n * max_ops]  task t's path from begin to end as run-length
+ *                      entries (run << 2 | op) at ops[t * max_ops ...]:
+ *                      XD_OP_M a_i against b_j, XD_OP_I b_j against a gap,
+ *                      XD_OP_D a_i against a gap
+ *   n_ops  uint32[n]   entries used; when more than max_ops are needed the
+ *                      task's status is XD_TASK_OPS_OVERFLOW, n_ops the count
+ *                      and its ops are not valid
+ * The codes of the steps (2 bits per band cell, 16 bytes per antidiagonal)
+ * are kept in device scratch of at most trace_budget bytes (0 = 4 GiB; a
+ * task larger than the budget runs alone); tasks run in sub-batches that fit.
+ * Synchronous on hip_stream (the sub-batches are planned on the host). */
+#define XD_OP_M 0
+#define XD_OP_I 1
+#define XD_OP_D 2
+int xd_banded_traceback(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,
+                        const int32_t* w, int32_t w_scalar, uint64_t n, int32_t k, int32_t match,
+                        int32_t mismatch, int32_t gap, uint32_t max_ops, uint64_t trace_budget,
+                        int32_t* score, uint32_t* beg, uint32_t* end, int32_t* status,
+                        uint64_t* cells, uint32_t* ops, uint32_t* n_ops, void* hip_stream);
 
 /* A captured batch: the batched form's kernels recorded once in a hipGraph
  * for fixed buffers (same meaning as xd_align_batch's) and replayed by

@@ -13,7 +13,8 @@ import numpy as np
 
 from . import _lib
 from ._lib import (BAND_MAX, READ_MAX, SCORE_LIMIT, TASK_BAD_READ, TASK_BAD_SEED,  # noqa
-                   TASK_BAD_X, TASK_BAND_OVERFLOW, TASK_NO_SEED, TASK_OK, X_MAX, XdropError)
+                   TASK_BAD_X, TASK_BAND_OVERFLOW, TASK_NO_SEED, TASK_OK, X_MAX, XdropError,
+                   TASK_OPS_OVERFLOW, TASK_TRACE_FAULT, OP_M, OP_I, OP_D)
 
 
 def _p(a) -> ctypes.c_void_p:
@@ -188,6 +189,36 @@ def banded_batch(store: ReadStore, pairs, seeds, w=None, w_scalar=32, k=17, matc
                                    int(k), int(match), int(mismatch), int(gap), _p(out["score"]),
                                    _p(out["end"]), _p(out["status"]), _p(out["cells"]),
                                    _stream_ptr(stream)))
+    return out
+
+
+def banded_traceback(store: ReadStore, pairs, seeds, w=None, w_scalar=32, k=17, match=1,
+                     mismatch=-1, gap=-1, max_ops=4096, trace_budget=0, stream=None):
+    """Banded Smith-Waterman with the alignment path (xd_banded_traceback).
+
+    Returns banded_batch's dict plus beg int32 [n, 2], ops int32 [n, max_ops]
+    (run-length entries run << 2 | op, op OP_M / OP_I / OP_D; the first
+    n_ops[t] of row t are valid) and n_ops int32 [n].  Synchronous."""
+    import torch
+    n = int(pairs.shape[0])
+    dev = pairs.device
+    _check_dev("pairs", pairs, 2 * n, 4)
+    _check_dev("seeds", seeds, 2 * n, 4)
+    if w is not None:
+        _check_dev("w", w, n, 4)
+    out = dict(score=torch.empty(n, dtype=torch.int32, device=dev),
+               beg=torch.empty((n, 2), dtype=torch.int32, device=dev),
+               end=torch.empty((n, 2), dtype=torch.int32, device=dev),
+               status=torch.empty(n, dtype=torch.int32, device=dev),
+               cells=torch.empty(n, dtype=torch.int64, device=dev),
+               ops=torch.empty((n, max(int(max_ops), 1)), dtype=torch.int32, device=dev),
+               n_ops=torch.empty(n, dtype=torch.int32, device=dev))
+    lib = _lib.load()
+    _lib.check(lib.xd_banded_traceback(
+        store.handle, _p(pairs), _p(seeds), _p(w), int(w_scalar), n, int(k), int(match),
+        int(mismatch), int(gap), int(max_ops), int(trace_budget), _p(out["score"]),
+        _p(out["beg"]), _p(out["end"]), _p(out["status"]), _p(out["cells"]), _p(out["ops"]),
+        _p(out["n_ops"]), _stream_ptr(stream)))
     return out
 
 

@@ -10,6 +10,8 @@ LIB_PATH = os.path.join(HERE, "libxdrop.so")
 XD_OK, XD_EINVAL, XD_ENOMEM, XD_EDEVICE, XD_EAGAIN = 0, -1, -2, -3, -4
 TASK_OK, TASK_BAD_READ, TASK_BAD_SEED, TASK_BAD_X, TASK_BAND_OVERFLOW = 0, 1, 2, 3, 4
 TASK_NO_SEED = 5
+TASK_OPS_OVERFLOW, TASK_TRACE_FAULT = 6, 7
+OP_M, OP_I, OP_D = 0, 1, 2
 X_MAX = 1 << 20
 BAND_MAX = 48
 SCORE_LIMIT = 127
@@ -21,7 +23,7 @@ OVERLAP_M_MAX = 64
 EXPORTS = (
     "xd_pack_reads", "xd_store_create", "xd_store_create_from_codes", "xd_store_destroy",
     "xd_store_info", "xd_align_batch", "xd_align_batch_persistent", "xd_align_pairs",
-    "xd_banded_batch", "xd_find_overlaps",
+    "xd_banded_batch", "xd_banded_traceback", "xd_find_overlaps",
     "xd_plan_create",
     "xd_plan_launch", "xd_plan_destroy", "xd_profile_enable", "xd_profile_read",
     "xd_server_request_bytes", "xd_server_fixed_bytes", "xd_server_create", "xd_server_submit", "xd_server_poll",
@@ -122,6 +124,9 @@ def load() -> ctypes.CDLL:
     lib.xd_banded_batch.argtypes = [vp, vp, vp, vp, i32, u64, i32, i32, i32, i32, vp, vp, vp,
                                     vp, vp]
     lib.xd_banded_batch.restype = ctypes.c_int
+    lib.xd_banded_traceback.argtypes = [vp, vp, vp, vp, i32, u64, i32, i32, i32, i32, u32, u64,
+                                        vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.xd_banded_traceback.restype = ctypes.c_int
     lib.xd_find_overlaps.argtypes = [vp, i32, u32, u32, u64, vp, vp, u64, vp,
                                      ctypes.POINTER(OverlapCounts), vp]
     lib.xd_find_overlaps.restype = ctypes.c_int

@@ -22,15 +22,20 @@
 
 #include <vector>
 
+#include "scan.h"
 #include "store_view.h"
 #include "xdrop.h"
 
 namespace {
 
+using xscan::Arena;
+using xscan::block_excl_scan;
+using xscan::grid_for;
+
 constexpr int kThreads = 256;
 constexpr int kChunk = 64;                   // k-mer starts per thread in the passes
-constexpr int kScanPer = 8;                  // items per thread in the scans
-constexpr int kScanTile = kThreads * kScanPer;
+constexpr int kScanPer = xscan::kPer;         // slots per thread in the table scans
+constexpr int kScanTile = xscan::kTile;
 constexpr int kSortPer = 16;                 // items per thread in the radix sort
 constexpr int kSortTile = kThreads * kSortPer;
 constexpr uint64_t kSaltB = 0x9e3779b97f4a7c15ull;
@@ -178,58 +183,6 @@ __global__ __launch_bounds__(kThreads) void k_table(KmerScan s, const unsigned l
     const uint32_t i = atomicAdd(&t.cnt[slot], 1u);
     if (i < t.m) t.loc[slot * t.m + i] = make_uint2(r, p);
   });
-}
-
-// ---- block scan and multi-level exclusive scan --------------------------------
-
-template <typename T>
-__device__ T block_excl_scan(T v, T& total) {
-  __shared__ T sh[kThreads];
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int o = 1; o < kThreads; o <<= 1) {
-    const T a = t >= o ? sh[t - o] : (T)0;
-    __syncthreads();
-    sh[t] += a;
-    __syncthreads();
-  }
-  total = sh[kThreads - 1];
-  const T incl = sh[t];
-  __syncthreads();
-  return incl - v;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scan_reduce(const T* in, uint64_t n, T* sums) {
-  const uint64_t b0 = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
-  T v = 0;
-  for (int u = 0; u < kScanPer; ++u)
-    if (b0 + u < n) v += in[b0 + u];
-  T total;
-  block_excl_scan(v, total);
-  if (threadIdx.x == 0) sums[blockIdx.x] = total;
-}
-
-// exclusive scan of each tile plus its tile offset (sums, or 0 when null);
-// the last tile also writes out[n] = the grand total.  out may alias in.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scan_down(const T* in, T* out, uint64_t n,
-                                                        const T* sums) {
-  const uint64_t b0 = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
-  T v[kScanPer];
-  T s = 0;
-  for (int u = 0; u < kScanPer; ++u) {
-    v[u] = b0 + u < n ? in[b0 + u] : (T)0;
-    s += v[u];
-  }
-  T total;
-  T run = block_excl_scan(s, total) + (sums ? sums[blockIdx.x] : (T)0);
-  for (int u = 0; u < kScanPer; ++u) {
-    if (b0 + u < n) out[b0 + u] = run;
-    run += v[u];
-  }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) out[n] = run;
 }
 
 // ---- retention and pair expansion ---------------------------------------------
@@ -432,51 +385,6 @@ int hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, #call); \
   } while (0)
 
-// stream-ordered scratch, released on the stream when it goes out of scope
-struct Arena {
-  hipStream_t st;
-  std::vector<void*> held;
-  explicit Arena(hipStream_t s) : st(s) {}
-  ~Arena() {
-    for (void* p : held) (void)hipFreeAsync(p, st);
-  }
-  template <typename T>
-  hipError_t get(T** p, uint64_t count) {
-    *p = nullptr;
-    hipError_t e = hipMallocAsync((void**)p, (count ? count : 1) * sizeof(T), st);
-    if (e == hipSuccess) held.push_back(*p);
-    return e;
-  }
-  void drop(void* p) {
-    for (auto& q : held)
-      if (q == p) {
-        (void)hipFreeAsync(q, st);
-        q = nullptr;
-      }
-  }
-};
-
-uint32_t grid_for(uint64_t n, uint64_t per) { return (uint32_t)((n + per - 1) / per); }
-
-// out[0..n] = exclusive scan of in[0..n) and its total; out may alias in
-template <typename T>
-int scan(Arena& ar, const T* in, T* out, uint64_t n) {
-  const uint32_t nb = grid_for(n ? n : 1, kScanTile);
-  if (nb == 1) {
-    hipLaunchKernelGGL(k_scan_down<T>, dim3(1), dim3(kThreads), 0, ar.st, in, out, n,
-                       (const T*)nullptr);
-    return XD_OK;
-  }
-  T* sums = nullptr;
-  OV_TRY(ar.get(&sums, (uint64_t)nb + 1));
-  hipLaunchKernelGGL(k_scan_reduce<T>, dim3(nb), dim3(kThreads), 0, ar.st, in, n, sums);
-  int rc = scan<T>(ar, sums, sums, nb);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_scan_down<T>, dim3(nb), dim3(kThreads), 0, ar.st, in, out, n,
-                     (const T*)sums);
-  return XD_OK;
-}
-
 template <typename T>
 int fetch(hipStream_t st, const T* dev, T* host, uint64_t count = 1) {
   OV_TRY(hipMemcpyAsync(host, dev, count * sizeof(T), hipMemcpyDeviceToHost, st));
@@ -591,7 +499,7 @@ extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, ui
     OV_TRY(ar.get(&d_rc, 1));
     OV_TRY(hipMemsetAsync(d_rc, 0, sizeof(RetainCtr), st));
     hipLaunchKernelGGL(k_retain_count, dim3(nb), dim3(kThreads), 0, st, t, blk, d_rc);
-    if ((rc = scan<uint64_t>(ar, blk, blk, nb))) return rc;
+    OV_TRY(xscan::exclusive_scan<uint64_t>(ar, blk, blk, nb));
     RetainCtr h_rc;
     if ((rc = fetch(st, d_rc, &h_rc))) return rc;
     cn.table_keys = h_rc.keys;
@@ -605,7 +513,7 @@ extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, ui
       OV_TRY(ar.get(&ret, cn.retained));
       OV_TRY(ar.get(&npair, cn.retained + 1));
       hipLaunchKernelGGL(k_retain_write, dim3(nb), dim3(kThreads), 0, st, t, blk, ret, npair);
-      if ((rc = scan<uint64_t>(ar, npair, npair, cn.retained))) return rc;
+      OV_TRY(xscan::exclusive_scan<uint64_t>(ar, npair, npair, cn.retained));
       if ((rc = fetch(st, npair + cn.retained, &cn.seeds))) return rc;
       if (cn.seeds >= 0xffffffffull)
         return fail(XD_EINVAL, "xd_find_overlaps: %llu seeds (limit 2^32 - 2); lower m",
@@ -631,7 +539,7 @@ extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, ui
         for (uint32_t sh = 0; sh < fbits[fi]; sh += 8) {
           hipLaunchKernelGGL(k_sort_hist, dim3(nt), dim3(kThreads), 0, st, cur, S, fields[fi],
                              (int)sh, hist);
-          if ((rc = scan<uint32_t>(ar, hist, hist, (uint64_t)nt * 256))) return rc;
+          OV_TRY(xscan::exclusive_scan<uint32_t>(ar, hist, hist, (uint64_t)nt * 256));
           hipLaunchKernelGGL(k_sort_scatter, dim3(nt), dim3(kThreads), 0, st, cur, alt, S,
                              fields[fi], (int)sh, hist);
           uint4* tmp = cur;
@@ -642,7 +550,7 @@ extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, ui
       OV_TRY(ar.get(&head, S + 1));
       hipLaunchKernelGGL(k_heads, dim3(grid_for(S, kThreads)), dim3(kThreads), 0, st, cur, S,
                          head);
-      if ((rc = scan<uint32_t>(ar, head, head, S))) return rc;
+      OV_TRY(xscan::exclusive_scan<uint32_t>(ar, head, head, S));
       uint32_t P = 0;
       if ((rc = fetch(st, head + S, &P))) return rc;
       cn.pairs = P;

@@ -27,12 +27,14 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "xdrop.h"
+#include "scan.h"
 #include "store_view.h"
 #include "xdrop_device.h"
 
@@ -611,27 +613,40 @@ struct BandedArgs {
   uint32_t* end;
   int32_t* status;
   uint64_t* cells;
+  // traced bands: task t = t0 + block; its codes start at entry
+  // 16 * (tr_off[t] - tr_off0) of tr_codes and its group bases at
+  // tr_off[t] - tr_off0 of tr_bases
+  uint32_t t0;
+  uint4* tr_codes;
+  uint32_t* tr_bases;
+  const uint64_t* tr_off;
+  uint64_t tr_off0;
 };
 
 constexpr int kBandedLdsWords = 256 + 17 + 32;
+constexpr int kTraceGroup = 16;  // antidiagonals per trace group (the kernel's GS)
+
+// per task: the status checks shared by the banded kernels
+__device__ __forceinline__ int32_t banded_status(const BandedArgs& A, uint32_t t, uint32_t ra,
+                                                 uint32_t rb, uint32_t pa, uint32_t pb,
+                                                 int32_t w) {
+  if (ra >= A.st.n_reads || rb >= A.st.n_reads) return XD_TASK_BAD_READ;
+  if ((uint64_t)pa + (uint64_t)A.k > A.st.len[ra] || (uint64_t)pb + (uint64_t)A.k > A.st.len[rb])
+    return XD_TASK_BAD_SEED;
+  if (w < 0 || w > xd::kBandedMaxW) return XD_TASK_BAD_X;
+  (void)t;
+  return XD_TASK_OK;
+}
 
 // One wavefront per task: band around the seed's diagonal over the whole reads.
-template <bool UNIT>
+template <bool UNIT, bool TRACE>
 __global__ __launch_bounds__(64) void k_banded(BandedArgs A) {
   __shared__ uint32_t ring[kBandedLdsWords];
-  const uint32_t t = blockIdx.x;
+  const uint32_t t = A.t0 + blockIdx.x;
   const uint32_t ra = A.pairs[2 * (uint64_t)t], rb = A.pairs[2 * (uint64_t)t + 1];
   const uint32_t pa = A.seeds[2 * (uint64_t)t], pb = A.seeds[2 * (uint64_t)t + 1];
   const int32_t w = A.w ? A.w[t] : A.w_scalar;
-  int32_t st = XD_TASK_OK;
-  if (ra >= A.st.n_reads || rb >= A.st.n_reads) {
-    st = XD_TASK_BAD_READ;
-  } else if ((uint64_t)pa + (uint64_t)A.k > A.st.len[ra] ||
-             (uint64_t)pb + (uint64_t)A.k > A.st.len[rb]) {
-    st = XD_TASK_BAD_SEED;
-  } else if (w < 0 || w > xd::kBandedMaxW) {
-    st = XD_TASK_BAD_X;
-  }
+  const int32_t st = banded_status(A, t, ra, rb, pa, pb, w);
   if (__builtin_amdgcn_readfirstlane(st) != XD_TASK_OK) {
     if (xd::lane_id() == 0) {
       A.score[t] = INT32_MIN;
@@ -650,7 +665,13 @@ __global__ __launch_bounds__(64) void k_banded(BandedArgs A) {
   bt.c = (int32_t)pa - (int32_t)pb;
   bt.w = w;
   ExtOut o;
-  xd::banded_sw<UNIT>(bt, A.sc, ring, o);
+  if constexpr (TRACE) {
+    const uint64_t g0 = A.tr_off[t] - A.tr_off0;
+    xd::banded_sw<UNIT, true>(bt, A.sc, ring, o,
+                              xd::BandTrace{A.tr_codes + g0 * kTraceGroup, A.tr_bases + g0});
+  } else {
+    xd::banded_sw<UNIT>(bt, A.sc, ring, o);
+  }
   if (xd::lane_id() == 0) {
     A.score[t] = o.best;
     A.end[2 * (uint64_t)t] = (uint32_t)o.bi;
@@ -658,6 +679,98 @@ __global__ __launch_bounds__(64) void k_banded(BandedArgs A) {
     A.status[t] = XD_TASK_OK;
     if (A.cells) A.cells[t] = o.cells;
   }
+}
+
+// trace groups of task t (0 when the task is invalid or its band misses the grid)
+__global__ __launch_bounds__(256) void k_band_groups(BandedArgs A, uint64_t* groups) {
+  const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= A.n) return;
+  const uint32_t ra = A.pairs[2 * t], rb = A.pairs[2 * t + 1];
+  const uint32_t pa = A.seeds[2 * t], pb = A.seeds[2 * t + 1];
+  const int32_t w = A.w ? A.w[t] : A.w_scalar;
+  uint64_t g = 0;
+  if (banded_status(A, (uint32_t)t, ra, rb, pa, pb, w) == XD_TASK_OK) {
+    const xd::BandSpan sp = xd::band_span((int32_t)A.st.len[ra], (int32_t)A.st.len[rb],
+                                          (int32_t)pa - (int32_t)pb, w);
+    if (sp.dlo <= sp.dhi) g = (uint64_t)(sp.d_last - sp.d_first + kTraceGroup) / kTraceGroup;
+  }
+  groups[t] = g;
+}
+
+struct TraceOut {
+  uint32_t t0, t1;  // tasks of this sub-batch
+  uint32_t max_ops;
+  uint32_t* ops;    // [n * max_ops]
+  uint32_t* n_ops;  // [n]
+  uint32_t* beg;    // [2 n]
+};
+
+// one thread per task: walk the stored codes back from the end cell to the
+// first cell whose H is 0, run-length encoding the steps, then reverse them
+__global__ __launch_bounds__(256) void k_band_traceback(BandedArgs A, TraceOut T) {
+  const uint64_t t = T.t0 + (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= T.t1) return;
+  uint32_t* ops = T.ops + t * T.max_ops;
+  int32_t i = (int32_t)A.end[2 * t], j = (int32_t)A.end[2 * t + 1];
+  if (A.status[t] != XD_TASK_OK || A.score[t] <= 0) {
+    T.beg[2 * t] = 0;
+    T.beg[2 * t + 1] = 0;
+    T.n_ops[t] = 0;
+    return;
+  }
+  const uint32_t ra = A.pairs[2 * t], rb = A.pairs[2 * t + 1];
+  const int32_t c = (int32_t)A.seeds[2 * t] - (int32_t)A.seeds[2 * t + 1];
+  const int32_t w = A.w ? A.w[t] : A.w_scalar;
+  const xd::BandSpan sp = xd::band_span((int32_t)A.st.len[ra], (int32_t)A.st.len[rb], c, w);
+  const uint64_t g0 = A.tr_off[t] - A.tr_off0;
+  const uint64_t n_ent = (A.tr_off[t + 1] - A.tr_off[t]) * kTraceGroup;
+  const uint4* codes = A.tr_codes + g0 * kTraceGroup;
+  const uint32_t* bases = A.tr_bases + g0;
+  uint32_t n = 0, run = 0, cur = 0;
+  bool fault = false;
+  while (i > 0 && j > 0) {
+    const int64_t e = (int64_t)(i + j) - sp.d_first;
+    if (e < 0 || (uint64_t)e >= n_ent) {
+      fault = true;
+      break;
+    }
+    const int32_t bit = i - (int32_t)bases[e / kTraceGroup];
+    if (bit < 0 || bit > 63) {
+      fault = true;
+      break;
+    }
+    const uint4 v = codes[e];
+    const uint32_t lo = bit < 32 ? v.x >> bit : v.y >> (bit - 32);
+    const uint32_t hi = bit < 32 ? v.z >> bit : v.w >> (bit - 32);
+    const uint32_t code = (lo & 1u) | ((hi & 1u) << 1);
+    if (code == 0) break;
+    // ops: 0 = M (from the diagonal), 2 = D (from (i-1, j)), 1 = I (from (i, j-1))
+    const uint32_t op = code == 1 ? XD_OP_M : code == 2 ? XD_OP_D : XD_OP_I;
+    if (run && op != cur) {
+      if (n < T.max_ops) ops[n] = run << 2 | cur;
+      ++n;
+      run = 0;
+    }
+    cur = op;
+    ++run;
+    if (code != 3) --i;
+    if (code != 2) --j;
+  }
+  if (run) {
+    if (n < T.max_ops) ops[n] = run << 2 | cur;
+    ++n;
+  }
+  if (n <= T.max_ops)
+    for (uint32_t a = 0, b = n; a + 1 < b; ++a, --b) {
+      const uint32_t x = ops[a];
+      ops[a] = ops[b - 1];
+      ops[b - 1] = x;
+    }
+  T.beg[2 * t] = (uint32_t)i;
+  T.beg[2 * t + 1] = (uint32_t)j;
+  T.n_ops[t] = n;
+  if (fault) A.status[t] = XD_TASK_TRACE_FAULT;
+  else if (n > T.max_ops) A.status[t] = XD_TASK_OPS_OVERFLOW;
 }
 
 // ---- launch sequences -------------------------------------------------------
@@ -1226,13 +1339,89 @@ int xd_banded_batch(const xd_store* store, const uint32_t* pairs, const uint32_t
   A.end = end;
   A.status = status;
   A.cells = cells;
+  A.t0 = 0;
+  A.tr_codes = nullptr;
+  A.tr_bases = nullptr;
+  A.tr_off = nullptr;
+  A.tr_off0 = 0;
   hipStream_t stream = (hipStream_t)hip_stream;
   if (match == 1)
-    hipLaunchKernelGGL(k_banded<true>, dim3((uint32_t)n), dim3(64), 0, stream, A);
+    hipLaunchKernelGGL((k_banded<true, false>), dim3((uint32_t)n), dim3(64), 0, stream, A);
   else
-    hipLaunchKernelGGL(k_banded<false>, dim3((uint32_t)n), dim3(64), 0, stream, A);
+    hipLaunchKernelGGL((k_banded<false, false>), dim3((uint32_t)n), dim3(64), 0, stream, A);
   hipError_t le = hipGetLastError();
   if (le != hipSuccess) return hip_fail(le, "kernel launch");
+  return XD_OK;
+}
+
+int xd_banded_traceback(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,
+                        const int32_t* w, int32_t w_scalar, uint64_t n, int32_t k, int32_t match,
+                        int32_t mismatch, int32_t gap, uint32_t max_ops, uint64_t trace_budget,
+                        int32_t* score, uint32_t* beg, uint32_t* end, int32_t* status,
+                        uint64_t* cells, uint32_t* ops, uint32_t* n_ops, void* hip_stream) {
+  if (!store) return fail(XD_EINVAL, "xd_banded_traceback: store is null");
+  int rc = check_scoring(k, match, mismatch, gap);
+  if (rc) return rc;
+  if (!w && (w_scalar < 0 || w_scalar > XD_BAND_MAX))
+    return fail(XD_EINVAL, "w_scalar must be in [0, %d] (got %d)", XD_BAND_MAX, w_scalar);
+  if (n > (1ull << 30)) return fail(XD_EINVAL, "n = %llu exceeds 2^30", (unsigned long long)n);
+  if (n && (!pairs || !seeds || !score || !beg || !end || !status || !n_ops ||
+            (max_ops && !ops)))
+    return fail(XD_EINVAL, "xd_banded_traceback: null task or result array");
+  if (n == 0) return XD_OK;
+  BandedArgs A;
+  A.st = {store->words, store->word_off, store->len, store->n_reads};
+  A.pairs = pairs;
+  A.seeds = seeds;
+  A.w = w;
+  A.w_scalar = w_scalar;
+  A.n = (uint32_t)n;
+  A.k = k;
+  A.sc = {match, mismatch, gap};
+  A.score = score;
+  A.end = end;
+  A.status = status;
+  A.cells = cells;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  xscan::Arena ar(stream);
+  // trace groups per task, their offsets, and sub-batches that fit the budget
+  uint64_t* off = nullptr;
+  HIP_TRY(ar.get(&off, n + 1));
+  hipLaunchKernelGGL(k_band_groups, dim3(xscan::grid_for(n, 256)), dim3(256), 0, stream, A, off);
+  HIP_TRY(xscan::exclusive_scan<uint64_t>(ar, off, off, n));
+  std::vector<uint64_t> h(n + 1);
+  HIP_TRY(hipMemcpyAsync(h.data(), off, (n + 1) * 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  const uint64_t group_bytes = kTraceGroup * sizeof(uint4) + sizeof(uint32_t);
+  uint64_t cap = (trace_budget ? trace_budget : (4ull << 30)) / group_bytes;
+  for (uint64_t t = 0; t < n; ++t) cap = std::max(cap, h[t + 1] - h[t]);
+  cap = std::max<uint64_t>(std::min(cap, h[n]), 1);
+  uint4* codes = nullptr;
+  uint32_t* bases = nullptr;
+  HIP_TRY(ar.get(&codes, cap * kTraceGroup));
+  HIP_TRY(ar.get(&bases, cap));
+  A.tr_codes = codes;
+  A.tr_bases = bases;
+  A.tr_off = off;
+  for (uint64_t t0 = 0; t0 < n;) {
+    uint64_t t1 = t0 + 1;
+    while (t1 < n && h[t1 + 1] - h[t0] <= cap) ++t1;
+    A.t0 = (uint32_t)t0;
+    A.tr_off0 = h[t0];
+    if (match == 1)
+      hipLaunchKernelGGL((k_banded<true, true>), dim3((uint32_t)(t1 - t0)), dim3(64), 0, stream,
+                         A);
+    else
+      hipLaunchKernelGGL((k_banded<false, true>), dim3((uint32_t)(t1 - t0)), dim3(64), 0, stream,
+                         A);
+    TraceOut T{(uint32_t)t0, (uint32_t)t1, max_ops, ops, n_ops, beg};
+    hipLaunchKernelGGL(k_band_traceback, dim3(xscan::grid_for(t1 - t0, 256)), dim3(256), 0,
+                       stream, A, T);
+    t0 = t1;
+  }
+  hipError_t le = hipGetLastError();
+  if (le != hipSuccess) return hip_fail(le, "kernel launch");
+  HIP_TRY(hipStreamSynchronize(stream));
   return XD_OK;
 }
 

@@ -826,6 +826,13 @@ struct BandTask {
   int32_t c, w;        // band: |i - j - c| <= w
 };
 
+// lane L of v takes the wave-uniform value x (v_writelane_b32; no load)
+template <int L>
+__device__ __forceinline__ void write_lane(uint32_t& v, uint32_t x) {
+  x = __builtin_amdgcn_readfirstlane(x);
+  asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "n"(L));
+}
+
 // bits lo..hi of a 64-bit lane mask (empty when hi < lo; lo, hi clamped)
 __device__ __forceinline__ uint64_t lane_range(int32_t lo, int32_t hi) {
   lo = max(lo, 0);
@@ -835,9 +842,37 @@ __device__ __forceinline__ uint64_t lane_range(int32_t lo, int32_t hi) {
   return top & ~((1ull << lo) - 1ull);
 }
 
-template <bool UNIT>
+// the band's diagonals delta = i - j that meet the grid [dlo, dhi] (empty when
+// dlo > dhi) and its first and last antidiagonal holding band cells: diagonal
+// delta starts at i + j = 2 + |delta| and ends at min(la, lb+delta) + min(lb, la-delta)
+struct BandSpan {
+  int32_t dlo, dhi, d_first, d_last;
+};
+
+__device__ __forceinline__ BandSpan band_span(int32_t la, int32_t lb, int32_t c, int32_t w) {
+  BandSpan b;
+  b.dlo = max(c - w, 1 - lb);
+  b.dhi = (la > 0 && lb > 0) ? min(c + w, la - 1) : b.dlo - 1;
+  b.d_first = 2 + (b.dlo > 0 ? b.dlo : (b.dhi < 0 ? -b.dhi : 0));
+  const int32_t dpk = min(max(la - lb, b.dlo), b.dhi);
+  b.d_last = dpk <= la - lb ? 2 * lb + dpk : 2 * la - dpk;
+  return b;
+}
+
+// where a traced band writes its cells' steps: 2-bit codes (0 = H is 0, 1 =
+// from (i-1, j-1), 2 = from (i-1, j), 3 = from (i, j-1)) as two bit planes
+// per antidiagonal d (entry d - d_first: x|y<<32 = low bits, z|w<<32 = high
+// bits, bit l for row base + l), and the window base row of each group of 16
+// antidiagonals
+struct BandTrace {
+  uint4* codes;
+  uint32_t* bases;
+};
+
+template <bool UNIT, bool TRACE = false>
 __device__ __forceinline__ void banded_sw(const BandTask& e, const Scoring& sc,
-                                          uint32_t* __restrict__ ring, ExtOut& res) {
+                                          uint32_t* __restrict__ ring, ExtOut& res,
+                                          BandTrace tr = BandTrace{nullptr, nullptr}) {
   constexpr int GS = 16;
   constexpr int RING = 256, MASK = RING - 1, MIR = GS + 1, RA = 128;
   const int lane = lane_id();
@@ -850,8 +885,8 @@ __device__ __forceinline__ void banded_sw(const BandTask& e, const Scoring& sc,
   const int32_t w = __builtin_amdgcn_readfirstlane(e.w);
   const int32_t bias = kBias0;
   // band diagonals that meet the grid, and the cells on them
-  const int32_t dlo = max(c - w, 1 - lb);
-  const int32_t dhi = (la > 0 && lb > 0) ? min(c + w, la - 1) : dlo - 1;
+  const BandSpan sp = band_span(la, lb, c, w);
+  const int32_t dlo = sp.dlo, dhi = sp.dhi;
   uint32_t cnt = 0;
   for (int32_t dl = dlo + lane; dl <= dhi; dl += 64)
     cnt += (uint32_t)(min(la, lb + dl) - max(1, 1 + dl) + 1);
@@ -861,11 +896,7 @@ __device__ __forceinline__ void banded_sw(const BandTask& e, const Scoring& sc,
   res.bj = 0;
   res.flags = kExtDone;
   if (dlo > dhi) return;
-  // first and last antidiagonal with band cells: diagonal delta starts at
-  // i + j = 2 + |delta| and ends at min(la, lb+delta) + min(lb, la-delta)
-  const int32_t d_first = 2 + (dlo > 0 ? dlo : (dhi < 0 ? -dhi : 0));
-  const int32_t dpk = min(max(la - lb, dlo), dhi);
-  const int32_t d_last = dpk <= la - lb ? 2 * lb + dpk : 2 * la - dpk;
+  const int32_t d_first = sp.d_first, d_last = sp.d_last;
   // band rows on antidiagonal dd, inside the grid
   auto row_lo = [&](int32_t dd) { return max(max(1, dd - lb), (dd + c - w + 1) >> 1); };
   auto row_hi = [&](int32_t dd) { return min(min(la, dd - 1), (dd + c + w) >> 1); };
@@ -945,6 +976,7 @@ __device__ __forceinline__ void banded_sw(const BandTask& e, const Scoring& sc,
 #pragma unroll
     for (int t = 0; t < GS; ++t) bmv[t] = rbytes[ad + 4 * t];
     uint64_t imp[GS][1];
+    uint32_t trc[4] = {0, 0, 0, 0};  // lane t: step t's code planes (traced bands)
     uint64_t last = 0;
     int32_t lastt = 0;
     const int32_t thr0 = thr;
@@ -962,10 +994,23 @@ __device__ __forceinline__ void banded_sw(const BandTask& e, const Scoring& sc,
       }
       const int32_t upv = shr1_zero(U1);
       const int32_t dg = max(Up, fl2);
-      int32_t s = max(max(dg + (int32_t)bmv[t] + C, upv), U1);
+      const int32_t dgs = dg + (int32_t)bmv[t] + C;
+      int32_t s = max(max(dgs, upv), U1);
       s = max(s, fl);
       const bool in = __builtin_amdgcn_inverse_ballot_w64(m);
       const int32_t u = in ? s : 0;
+      if constexpr (TRACE) {
+        // the step that produced H: diagonal first, then (i-1, j), then (i, j-1);
+        // 0 where H is 0.  Out-of-band neighbours hold 0 < fl and never match.
+        const uint64_t pos = m & ballot64(s > fl);
+        const uint64_t isd = ballot64(s == dgs);
+        const uint64_t isu = ballot64(s == upv);
+        const uint64_t b0 = pos & (isd | ~isu), b1 = pos & ~isd;
+        write_lane<t>(trc[0], (uint32_t)b0);
+        write_lane<t>(trc[1], (uint32_t)(b0 >> 32));
+        write_lane<t>(trc[2], (uint32_t)b1);
+        write_lane<t>(trc[3], (uint32_t)(b1 >> 32));
+      }
       const uint64_t im = ballot64(u > thr);
       Up = upv;
       U1 = u;
@@ -997,6 +1042,12 @@ __device__ __forceinline__ void banded_sw(const BandTask& e, const Scoring& sc,
     } else if (lastt) {
       bi = base + (int32_t)__builtin_ctzll(last);
       dstar = d + lastt - 1;
+    }
+    if constexpr (TRACE) {
+      const int32_t e0 = d - d_first;  // entry of this group's first antidiagonal
+      if (lane < GS && d + lane <= d_last)
+        tr.codes[e0 + lane] = make_uint4(trc[0], trc[1], trc[2], trc[3]);
+      if (lane == 0) tr.bases[e0 / GS] = (uint32_t)base;
     }
     d += GS;
   }
