@@ -4,7 +4,10 @@ Workload c2 (100,000 read pairs from a 30x 4.6 Mbp read set, one true seed
 each): each task aligns the two whole reads within w of the seed's diagonal.
 One JSON line per band half-width; the oracle is timed on a sample.
 
-    python bench_banded.py [--w 16 32 48] [--steps 5] [--warmup 1] [--cpu-tasks 300]
+    python bench_banded.py [--w 16 32 48] [--steps 5] [--warmup 1] [--cpu-tasks 300] [--trace]
+
+With --trace each width also gets a line for xd_banded_traceback (the same
+alignments plus begin cells and run-length paths).
 """
 import argparse
 import json
@@ -25,6 +28,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-tasks", type=int, default=300)
+    ap.add_argument("--trace", action="store_true", help="also time xd_banded_traceback")
+    ap.add_argument("--max-ops", type=int, default=16384)
+    ap.add_argument("--trace-budget", type=int, default=0, help="bytes (0: the library's)")
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -70,6 +76,31 @@ def main():
                                     "sample": "first %d tasks (%.1f s), scores checked against "
                                               "the GPU's" % (idx.size, dt)}
         print(json.dumps(line), flush=True)
+        if args.trace:
+            run_t = lambda: xd.banded_traceback(store, pairs, seeds, w_scalar=wd, k=w.k,  # noqa
+                                                max_ops=args.max_ops,
+                                                trace_budget=args.trace_budget)
+            for _ in range(args.warmup):
+                tr = run_t()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                tr = run_t()
+            torch.cuda.synchronize()
+            mst = (time.perf_counter() - t0) * 1e3 / args.steps
+            if not torch.equal(tr["score"], out["score"]):
+                raise RuntimeError("traced and untraced scores differ")
+            n_ops = tr["n_ops"].cpu().numpy()
+            print(json.dumps({
+                "metric": "banded Smith-Waterman with traceback (xd_banded_traceback)", "w": wd,
+                "tasks": w.n_tasks, "ms_per_step": round(mst, 3),
+                "gcups": round(cells / (mst / 1e3) / 1e9, 2),
+                "pairs_per_s": round(w.n_tasks / (mst / 1e3), 1),
+                "ops_mean": round(float(n_ops.mean()), 1), "ops_max": int(n_ops.max()),
+                "ops_over_capacity": int((n_ops > args.max_ops).sum()), "max_ops": args.max_ops,
+                "trace_budget": args.trace_budget or "32 GiB",
+                "dtype": "int32", "data": "synthetic",
+                "config": line["config"]}), flush=True)
     store.close()
 
 

@@ -285,7 +285,8 @@ int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, uint32_t bloo
  *                      task's status is XD_TASK_OPS_OVERFLOW, n_ops the count
  *                      and its ops are not valid
  * The codes of the steps (2 bits per band cell, 16 bytes per antidiagonal)
- * are kept in device scratch of at most trace_budget bytes (0 = 4 GiB; a
+ * are kept in device scratch of at most trace_budget bytes (0 = 32 GiB,
+ * allocated only as far as the batch needs; a
  * task larger than the budget runs alone); tasks run in sub-batches that fit.
  * Synchronous on hip_stream (the sub-batches are planned on the host). */
 #define XD_OP_M 0

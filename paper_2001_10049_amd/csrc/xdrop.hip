@@ -723,26 +723,71 @@ __global__ __launch_bounds__(256) void k_band_traceback(BandedArgs A, TraceOut T
   const int32_t w = A.w ? A.w[t] : A.w_scalar;
   const xd::BandSpan sp = xd::band_span((int32_t)A.st.len[ra], (int32_t)A.st.len[rb], c, w);
   const uint64_t g0 = A.tr_off[t] - A.tr_off0;
-  const uint64_t n_ent = (A.tr_off[t + 1] - A.tr_off[t]) * kTraceGroup;
+  const int64_t n_ent = (int64_t)(A.tr_off[t + 1] - A.tr_off[t]) * kTraceGroup;
   const uint4* codes = A.tr_codes + g0 * kTraceGroup;
   const uint32_t* bases = A.tr_bases + g0;
   uint32_t n = 0, run = 0, cur = 0;
   bool fault = false;
-  while (i > 0 && j > 0) {
-    const int64_t e = (int64_t)(i + j) - sp.d_first;
-    if (e < 0 || (uint64_t)e >= n_ent) {
+  // The walk visits entries e = i + j - d_first downwards, one or two at a
+  // time: it holds the aligned 4-entry block containing e (and that group's
+  // base) and has the block (and base) before it already in flight.
+  int64_t e = (int64_t)(i + j) - sp.d_first;
+  if (e < 0 || e >= n_ent) {  // the end cell is not in the stored band
+    T.beg[2 * t] = 0;
+    T.beg[2 * t + 1] = 0;
+    T.n_ops[t] = 0;
+    A.status[t] = XD_TASK_TRACE_FAULT;
+    return;
+  }
+  const uint4 zero = make_uint4(0, 0, 0, 0);
+  int64_t blk = e >> 2, grp = e >> 4;
+  uint4 c0 = codes[4 * blk], c1 = codes[4 * blk + 1], c2 = codes[4 * blk + 2],
+        c3 = codes[4 * blk + 3];
+  uint4 q0 = zero, q1 = zero, q2 = zero, q3 = zero;
+  if (blk > 0) {
+    q0 = codes[4 * blk - 4];
+    q1 = codes[4 * blk - 3];
+    q2 = codes[4 * blk - 2];
+    q3 = codes[4 * blk - 1];
+  }
+  uint32_t gb = bases[grp], qb = grp > 0 ? bases[grp - 1] : 0u;
+  while (!fault && i > 0 && j > 0) {
+    e = (int64_t)(i + j) - sp.d_first;
+    if (e < 0) {
       fault = true;
       break;
     }
-    const int32_t bit = i - (int32_t)bases[e / kTraceGroup];
-    if (bit < 0 || bit > 63) {
+    if ((e >> 2) != blk) {  // stepped into the block before
+      --blk;
+      c0 = q0;
+      c1 = q1;
+      c2 = q2;
+      c3 = q3;
+      if (blk > 0) {
+        q0 = codes[4 * blk - 4];
+        q1 = codes[4 * blk - 3];
+        q2 = codes[4 * blk - 2];
+        q3 = codes[4 * blk - 1];
+      }
+    }
+    if ((e >> 4) != grp) {
+      --grp;
+      gb = qb;
+      if (grp > 0) qb = bases[grp - 1];
+    }
+    const int32_t bit = i - (int32_t)gb;
+    if ((e >> 2) != blk || (e >> 4) != grp || bit < 0 || bit > 63) {
       fault = true;
       break;
     }
-    const uint4 v = codes[e];
-    const uint32_t lo = bit < 32 ? v.x >> bit : v.y >> (bit - 32);
-    const uint32_t hi = bit < 32 ? v.z >> bit : v.w >> (bit - 32);
-    const uint32_t code = (lo & 1u) | ((hi & 1u) << 1);
+    // component-wise selects keep the block in registers
+    const uint32_t sel = (uint32_t)e & 3u;
+    const uint32_t vx = sel == 0 ? c0.x : sel == 1 ? c1.x : sel == 2 ? c2.x : c3.x;
+    const uint32_t vy = sel == 0 ? c0.y : sel == 1 ? c1.y : sel == 2 ? c2.y : c3.y;
+    const uint32_t vz = sel == 0 ? c0.z : sel == 1 ? c1.z : sel == 2 ? c2.z : c3.z;
+    const uint32_t vw = sel == 0 ? c0.w : sel == 1 ? c1.w : sel == 2 ? c2.w : c3.w;
+    const uint64_t plane0 = (uint64_t)vy << 32 | vx, plane1 = (uint64_t)vw << 32 | vz;
+    const uint32_t code = (uint32_t)((plane0 >> bit) & 1u) | (uint32_t)(((plane1 >> bit) & 1u) << 1);
     if (code == 0) break;
     // ops: 0 = M (from the diagonal), 2 = D (from (i-1, j)), 1 = I (from (i, j-1))
     const uint32_t op = code == 1 ? XD_OP_M : code == 2 ? XD_OP_D : XD_OP_I;
@@ -1393,7 +1438,7 @@ int xd_banded_traceback(const xd_store* store, const uint32_t* pairs, const uint
   HIP_TRY(hipMemcpyAsync(h.data(), off, (n + 1) * 8, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
   const uint64_t group_bytes = kTraceGroup * sizeof(uint4) + sizeof(uint32_t);
-  uint64_t cap = (trace_budget ? trace_budget : (4ull << 30)) / group_bytes;
+  uint64_t cap = (trace_budget ? trace_budget : (32ull << 30)) / group_bytes;
   for (uint64_t t = 0; t < n; ++t) cap = std::max(cap, h[t + 1] - h[t]);
   cap = std::max<uint64_t>(std::min(cap, h[n]), 1);
   uint4* codes = nullptr;

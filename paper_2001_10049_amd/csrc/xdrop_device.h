@@ -830,7 +830,7 @@ struct BandTask {
 template <int L>
 __device__ __forceinline__ void write_lane(uint32_t& v, uint32_t x) {
   x = __builtin_amdgcn_readfirstlane(x);
-  asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "n"(L));
+  asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "n"(L));
 }
 
 // bits lo..hi of a 64-bit lane mask (empty when hi < lo; lo, hi clamped)
