@@ -1,4 +1,4 @@
-"""Every task of the full-size workloads c2, c3 and c5 against the oracle.
+"""Every task of the full-size workloads c2, c3, c4 and c5 against the oracle.
 
 The oracle's results for each workload were recorded once as chunked SHA-256
 digests by tests/golden/make_oracle_digests.py (a script that runs only the
@@ -47,7 +47,7 @@ def check_against_record(w, got, rec, label):
 
 
 @pytest.mark.parametrize("name,forms", [("c2", ("plain", "persistent")), ("c3", ("persistent",)),
-                                        ("c5", ("persistent",))])
+                                        ("c5", ("persistent",)), ("c4", ("persistent",))])
 def test_every_task_matches_oracle_record(name, forms):
     if name not in DIGESTS:
         pytest.skip("no oracle record for %s" % name)
