@@ -258,14 +258,17 @@ typedef struct {
  * written and XD_EAGAIN is returned with the counts filled in.  The result is
  * deterministic.  1 <= k <= XD_OVERLAP_K_MAX, 1 <= m <= XD_OVERLAP_M_MAX;
  * bloom_bits = bits of the first filter per k-mer occurrence (0 = 16, else
- * 4..64; a speed/memory setting that does not change the result).  Device
+ * 4..64) and table_slots = the hash table's first capacity (0 = estimated
+ * from the filters; rounded up to a power of two, at least 4096; a table
+ * that fills up is doubled and its pass rerun): speed/memory settings that
+ * do not change the result.  Device
  * scratch is taken from the stream's memory pool: about bloom_bits/8 bytes
  * per k-mer for the filter plus (12 + 8 m) bytes per hash-table slot, the
  * table sized at twice the repeated occurrences.  Runs on hip_stream and
  * returns when done (the counts need host round trips).  More than 2^32 - 2
  * k-mers or seeds -> XD_EINVAL. */
 int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, uint32_t bloom_bits,
-                     uint64_t max_pairs, uint32_t* pairs, uint64_t* seed_off,
+                     uint64_t table_slots, uint64_t max_pairs, uint32_t* pairs, uint64_t* seed_off,
                      uint64_t max_seeds, uint32_t* seeds, xd_overlap_counts* counts,
                      void* hip_stream);
 

@@ -222,7 +222,8 @@ def banded_traceback(store: ReadStore, pairs, seeds, w=None, w_scalar=32, k=17, 
     return out
 
 
-def find_overlaps(store: ReadStore, k=17, m=8, bloom_bits=0, capacity=None, stream=None):
+def find_overlaps(store: ReadStore, k=17, m=8, bloom_bits=0, capacity=None, stream=None,
+                  table_slots=0):
     """Candidate read pairs sharing a retained k-mer (xd_find_overlaps).
 
     capacity: (max_pairs, max_seeds) to allocate at once; None asks the
@@ -234,17 +235,18 @@ def find_overlaps(store: ReadStore, k=17, m=8, bloom_bits=0, capacity=None, stre
     cnt = _lib.OverlapCounts()
     st = _stream_ptr(stream)
     if capacity is None:
-        _lib.check(lib.xd_find_overlaps(store.handle, int(k), int(m), int(bloom_bits), 0, None,
-                                        None, 0, None, ctypes.byref(cnt), st))
+        _lib.check(lib.xd_find_overlaps(store.handle, int(k), int(m), int(bloom_bits),
+                                        int(table_slots), 0, None, None, 0, None,
+                                        ctypes.byref(cnt), st))
         capacity = (cnt.pairs, cnt.seeds)
     max_pairs, max_seeds = int(capacity[0]), int(capacity[1])
     dev = torch.device("cuda", torch.cuda.current_device())
     pairs = torch.empty((max(max_pairs, 1), 2), dtype=torch.int32, device=dev)
     seed_off = torch.empty(max_pairs + 1, dtype=torch.int64, device=dev)
     seeds = torch.empty((max(max_seeds, 1), 2), dtype=torch.int32, device=dev)
-    _lib.check(lib.xd_find_overlaps(store.handle, int(k), int(m), int(bloom_bits), max_pairs,
-                                    _p(pairs), _p(seed_off), max_seeds, _p(seeds),
-                                    ctypes.byref(cnt), st))
+    _lib.check(lib.xd_find_overlaps(store.handle, int(k), int(m), int(bloom_bits),
+                                    int(table_slots), max_pairs, _p(pairs), _p(seed_off),
+                                    max_seeds, _p(seeds), ctypes.byref(cnt), st))
     counts = {f: int(getattr(cnt, f)) for f, _ in _lib.OverlapCounts._fields_}
     P, S = counts["pairs"], counts["seeds"]
     return dict(pairs=pairs[:P], seed_off=seed_off[:P + 1], seeds=seeds[:S], counts=counts)

@@ -127,7 +127,7 @@ def load() -> ctypes.CDLL:
     lib.xd_banded_traceback.argtypes = [vp, vp, vp, vp, i32, u64, i32, i32, i32, i32, u32, u64,
                                         vp, vp, vp, vp, vp, vp, vp, vp]
     lib.xd_banded_traceback.restype = ctypes.c_int
-    lib.xd_find_overlaps.argtypes = [vp, i32, u32, u32, u64, vp, vp, u64, vp,
+    lib.xd_find_overlaps.argtypes = [vp, i32, u32, u32, u64, u64, vp, vp, u64, vp,
                                      ctypes.POINTER(OverlapCounts), vp]
     lib.xd_find_overlaps.restype = ctypes.c_int
     lib.xd_plan_create.argtypes = batch + [ctypes.POINTER(Tuning), ctypes.POINTER(vp)]

@@ -38,6 +38,7 @@ constexpr int kScanPer = xscan::kPer;         // slots per thread in the table s
 constexpr int kScanTile = xscan::kTile;
 constexpr int kSortPer = 16;                 // items per thread in the radix sort
 constexpr int kSortTile = kThreads * kSortPer;
+constexpr uint64_t kMaxProbe = 1024;       // longest linear probe before the table regrows
 constexpr uint64_t kSaltB = 0x9e3779b97f4a7c15ull;
 constexpr uint64_t kSaltT = 0xd1b54a32d192ed03ull;
 
@@ -156,6 +157,7 @@ struct Table {
 };
 
 // pass 2: the k-mers in B into the table; ctr[2] = 1 when a key found no slot
+// within kMaxProbe probes (the host then doubles the table and reruns the pass)
 __global__ __launch_bounds__(kThreads) void k_table(KmerScan s, const unsigned long long* B,
                                                     uint64_t WB, Table t,
                                                     unsigned long long* ctr) {
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(kThreads) void k_table(KmerScan s, const unsigned l
     const unsigned long long key = code + 1;
     uint64_t slot = fmix64(code ^ kSaltT) & (t.cap - 1);
     for (uint64_t probe = 0;; ++probe) {
-      if (probe == t.cap) {
+      if (probe == t.cap || probe == kMaxProbe) {  // full or crowded: the host regrows it
         atomicOr(&ctr[2], 1ull);
         return;
       }
@@ -397,7 +399,8 @@ uint32_t bit_length(uint64_t v) { return v ? 64u - (uint32_t)__builtin_clzll(v) 
 }  // namespace
 
 extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, uint32_t bloom_bits,
-                                uint64_t max_pairs, uint32_t* pairs, uint64_t* seed_off,
+                                uint64_t table_slots, uint64_t max_pairs, uint32_t* pairs,
+                                uint64_t* seed_off,
                                 uint64_t max_seeds, uint32_t* seeds, xd_overlap_counts* counts,
                                 void* hip_stream) {
   StoreView sv;
@@ -465,7 +468,11 @@ extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, ui
     const double f = (double)h_ctr[1] / (64.0 * (double)WB);
     const double expect = (double)h_ctr[0] + 2.0 * f * f * f * (double)cn.kmers;
     uint64_t cap = 4096;
-    while ((double)cap < 2.0 * expect + 1024.0) cap <<= 1;
+    if (table_slots) {
+      while (cap < table_slots && cap < (1ull << 32)) cap <<= 1;
+    } else {
+      while ((double)cap < 2.0 * expect + 1024.0) cap <<= 1;
+    }
 
     Table t{};
     t.m = m;

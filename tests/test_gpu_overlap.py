@@ -99,6 +99,24 @@ def test_c2_small_exact_and_filter_sizes():
         assert_same(got, ref, "c2-small bloom_bits=%d" % bits)
 
 
+def test_table_regrowth():
+    # a first table far too small fills up; it is doubled and the pass rerun
+    # (about seven times here) without changing the result
+    w = synth.config("c2-small")
+    ref = gpu(w.codes, w.off, w.length, 17, 8)
+    with xd.ReadStore.from_workload(w) as st:
+        r = xd.find_overlaps(st, k=17, m=8, table_slots=4096)
+        torch.cuda.synchronize()
+        got = (r["pairs"].cpu().numpy().view(np.uint32).reshape(-1, 2),
+               r["seed_off"].cpu().numpy().view(np.uint64),
+               r["seeds"].cpu().numpy().view(np.uint32).reshape(-1, 2), r["counts"])
+    assert got[3]["table_slots"] > 4 * 4096 and got[3]["table_keys"] > 4096
+    for a, b in zip(got[:3], ref[:3]):
+        assert np.array_equal(a, b)
+    for f in EXACT + ("pairs", "seeds"):
+        assert got[3][f] == ref[3][f]
+
+
 def test_capacity_and_eagain():
     w = synth.config("c2-small")
     with xd.ReadStore.from_workload(w) as st:
