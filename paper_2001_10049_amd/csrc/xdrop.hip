@@ -706,9 +706,21 @@ struct TraceOut {
 };
 
 // one thread per task: walk the stored codes back from the end cell to the
-// first cell whose H is 0, run-length encoding the steps, then reverse them
-__global__ __launch_bounds__(256) void k_band_traceback(BandedArgs A, TraceOut T) {
-  const uint64_t t = T.t0 + (uint64_t)blockIdx.x * 256 + threadIdx.x;
+// first cell whose H is 0, run-length encoding the steps, then reverse them.
+// The walk visits entries e = i + j - d_first downwards, one or two at a
+// time.  The thread's current group of 16 entries sits in its own LDS column;
+// the group before it is loaded into registers a whole group ahead and
+// written to LDS when the walk reaches it.
+constexpr int kTraceThreads = 64;
+
+// the group's sixteen entries as plain locals (an array of them would be
+// kept in scratch memory)
+#define XD_TRACE_EACH(F) F(0) F(1) F(2) F(3) F(4) F(5) F(6) F(7) F(8) F(9) F(10) F(11) \
+  F(12) F(13) F(14) F(15)
+
+__global__ __launch_bounds__(kTraceThreads) void k_band_traceback(BandedArgs A, TraceOut T) {
+  __shared__ uint4 stage[kTraceGroup][kTraceThreads];
+  const uint64_t t = T.t0 + (uint64_t)blockIdx.x * kTraceThreads + threadIdx.x;
   if (t >= T.t1) return;
   uint32_t* ops = T.ops + t * T.max_ops;
   int32_t i = (int32_t)A.end[2 * t], j = (int32_t)A.end[2 * t + 1];
@@ -726,11 +738,6 @@ __global__ __launch_bounds__(256) void k_band_traceback(BandedArgs A, TraceOut T
   const int64_t n_ent = (int64_t)(A.tr_off[t + 1] - A.tr_off[t]) * kTraceGroup;
   const uint4* codes = A.tr_codes + g0 * kTraceGroup;
   const uint32_t* bases = A.tr_bases + g0;
-  uint32_t n = 0, run = 0, cur = 0;
-  bool fault = false;
-  // The walk visits entries e = i + j - d_first downwards, one or two at a
-  // time: it holds the aligned 4-entry block containing e (and that group's
-  // base) and has the block (and base) before it already in flight.
   int64_t e = (int64_t)(i + j) - sp.d_first;
   if (e < 0 || e >= n_ent) {  // the end cell is not in the stored band
     T.beg[2 * t] = 0;
@@ -739,55 +746,47 @@ __global__ __launch_bounds__(256) void k_band_traceback(BandedArgs A, TraceOut T
     A.status[t] = XD_TASK_TRACE_FAULT;
     return;
   }
-  const uint4 zero = make_uint4(0, 0, 0, 0);
-  int64_t blk = e >> 2, grp = e >> 4;
-  uint4 c0 = codes[4 * blk], c1 = codes[4 * blk + 1], c2 = codes[4 * blk + 2],
-        c3 = codes[4 * blk + 3];
-  uint4 q0 = zero, q1 = zero, q2 = zero, q3 = zero;
-  if (blk > 0) {
-    q0 = codes[4 * blk - 4];
-    q1 = codes[4 * blk - 3];
-    q2 = codes[4 * blk - 2];
-    q3 = codes[4 * blk - 1];
-  }
-  uint32_t gb = bases[grp], qb = grp > 0 ? bases[grp - 1] : 0u;
-  while (!fault && i > 0 && j > 0) {
+  int64_t grp = e >> 4;
+#define XD_TRACE_DECL(k) uint4 n##k;
+#define XD_TRACE_LOAD(k) n##k = codes[pg * kTraceGroup + k];
+#define XD_TRACE_STAGE(k) stage[k][threadIdx.x] = n##k;
+  XD_TRACE_EACH(XD_TRACE_DECL)
+  int64_t pg = grp;
+  XD_TRACE_EACH(XD_TRACE_LOAD)
+  XD_TRACE_EACH(XD_TRACE_STAGE)
+  // the group before (group 0 reloads itself: a valid address, never used)
+  pg = grp > 0 ? grp - 1 : 0;
+  XD_TRACE_EACH(XD_TRACE_LOAD)
+  uint32_t gb = bases[grp], nb = bases[pg];
+  uint32_t n = 0, run = 0, cur = 0;
+  bool fault = false;
+  while (i > 0 && j > 0) {
     e = (int64_t)(i + j) - sp.d_first;
     if (e < 0) {
       fault = true;
       break;
     }
-    if ((e >> 2) != blk) {  // stepped into the block before
-      --blk;
-      c0 = q0;
-      c1 = q1;
-      c2 = q2;
-      c3 = q3;
-      if (blk > 0) {
-        q0 = codes[4 * blk - 4];
-        q1 = codes[4 * blk - 3];
-        q2 = codes[4 * blk - 2];
-        q3 = codes[4 * blk - 1];
-      }
-    }
-    if ((e >> 4) != grp) {
+    if ((e >> 4) != grp) {  // stepped into the group before: its entries are in nxt
       --grp;
-      gb = qb;
-      if (grp > 0) qb = bases[grp - 1];
+      if ((e >> 4) != grp) {
+        fault = true;
+        break;
+      }
+      XD_TRACE_EACH(XD_TRACE_STAGE)
+      gb = nb;
+      pg = grp > 0 ? grp - 1 : 0;
+      XD_TRACE_EACH(XD_TRACE_LOAD)
+      nb = bases[pg];
     }
     const int32_t bit = i - (int32_t)gb;
-    if ((e >> 2) != blk || (e >> 4) != grp || bit < 0 || bit > 63) {
+    if (bit < 0 || bit > 63) {
       fault = true;
       break;
     }
-    // component-wise selects keep the block in registers
-    const uint32_t sel = (uint32_t)e & 3u;
-    const uint32_t vx = sel == 0 ? c0.x : sel == 1 ? c1.x : sel == 2 ? c2.x : c3.x;
-    const uint32_t vy = sel == 0 ? c0.y : sel == 1 ? c1.y : sel == 2 ? c2.y : c3.y;
-    const uint32_t vz = sel == 0 ? c0.z : sel == 1 ? c1.z : sel == 2 ? c2.z : c3.z;
-    const uint32_t vw = sel == 0 ? c0.w : sel == 1 ? c1.w : sel == 2 ? c2.w : c3.w;
-    const uint64_t plane0 = (uint64_t)vy << 32 | vx, plane1 = (uint64_t)vw << 32 | vz;
-    const uint32_t code = (uint32_t)((plane0 >> bit) & 1u) | (uint32_t)(((plane1 >> bit) & 1u) << 1);
+    const uint4 v = stage[e & (kTraceGroup - 1)][threadIdx.x];
+    const uint64_t plane0 = (uint64_t)v.y << 32 | v.x, plane1 = (uint64_t)v.w << 32 | v.z;
+    const uint32_t code =
+        (uint32_t)((plane0 >> bit) & 1u) | (uint32_t)(((plane1 >> bit) & 1u) << 1);
     if (code == 0) break;
     // ops: 0 = M (from the diagonal), 2 = D (from (i-1, j)), 1 = I (from (i, j-1))
     const uint32_t op = code == 1 ? XD_OP_M : code == 2 ? XD_OP_D : XD_OP_I;
@@ -817,6 +816,10 @@ __global__ __launch_bounds__(256) void k_band_traceback(BandedArgs A, TraceOut T
   if (fault) A.status[t] = XD_TASK_TRACE_FAULT;
   else if (n > T.max_ops) A.status[t] = XD_TASK_OPS_OVERFLOW;
 }
+#undef XD_TRACE_STAGE
+#undef XD_TRACE_LOAD
+#undef XD_TRACE_DECL
+#undef XD_TRACE_EACH
 
 // ---- launch sequences -------------------------------------------------------
 
@@ -1460,8 +1463,8 @@ int xd_banded_traceback(const xd_store* store, const uint32_t* pairs, const uint
       hipLaunchKernelGGL((k_banded<false, true>), dim3((uint32_t)(t1 - t0)), dim3(64), 0, stream,
                          A);
     TraceOut T{(uint32_t)t0, (uint32_t)t1, max_ops, ops, n_ops, beg};
-    hipLaunchKernelGGL(k_band_traceback, dim3(xscan::grid_for(t1 - t0, 256)), dim3(256), 0,
-                       stream, A, T);
+    hipLaunchKernelGGL(k_band_traceback, dim3(xscan::grid_for(t1 - t0, kTraceThreads)),
+                       dim3(kTraceThreads), 0, stream, A, T);
     t0 = t1;
   }
   hipError_t le = hipGetLastError();
