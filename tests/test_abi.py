@@ -103,3 +103,31 @@ def test_store_create_rejects_bad_layout():
                              woff.ctypes.data_as(ctypes.c_void_p),
                              length.ctypes.data_as(ctypes.c_void_p), 1, ctypes.byref(h))
     assert rc == _lib.XD_EINVAL
+
+
+def test_find_overlaps_rejects_null_store():
+    lib = _lib.load()
+    cnt = _lib.OverlapCounts()
+    rc = lib.xd_find_overlaps(ctypes.c_void_p(0), 17, 8, 0, 0, 0, None, None, 0, None,
+                              ctypes.byref(cnt), None)
+    assert rc == _lib.XD_EINVAL and b"store" in lib.xd_last_error()
+
+
+def test_banded_traceback_argument_errors_without_device():
+    lib = _lib.load()
+    dummy = ctypes.c_void_p(1)  # never dereferenced: scalar checks come first
+
+    def call(store, w_scalar=32, n=1, k=17, m=1, mm=-1, g=-1, arrays=None):
+        a = arrays or [None] * 8
+        return lib.xd_banded_traceback(store, None, None, None, w_scalar, n, k, m, mm, g, 64, 0,
+                                       *a, None)
+
+    assert call(ctypes.c_void_p(0)) == _lib.XD_EINVAL
+    assert b"store" in lib.xd_last_error()
+    assert call(dummy, k=0) == _lib.XD_EINVAL
+    assert call(dummy, mm=2) == _lib.XD_EINVAL
+    assert call(dummy, w_scalar=_lib.BAND_MAX + 1) == _lib.XD_EINVAL
+    assert call(dummy, w_scalar=-1) == _lib.XD_EINVAL
+    assert call(dummy, n=1) == _lib.XD_EINVAL          # null task and result arrays
+    assert call(dummy, n=(1 << 30) + 1) == _lib.XD_EINVAL
+    assert call(dummy, n=0) == _lib.XD_OK              # nothing to do
