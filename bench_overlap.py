@@ -9,7 +9,10 @@ Read set: workload c2's (13,743 reads, 138 Mbp, 30x of a 4.6 Mbp genome,
             seeds at least k apart (X = 25, +1/-1/-1); ms and GCUPS
 The oracle's sort-based form is timed on a sample of the reads.
 
-    python bench_overlap.py [--steps 5] [--warmup 1] [--cpu-reads 1700]
+    python bench_overlap.py [--steps 5] [--warmup 1] [--cpu-reads 1700] [--workload c2|c4]
+
+--workload c4 runs the stage alone on c4's read set (250,273 reads, 3 Gbp, 30x
+of a 100 Mbp genome with 10 % repeats, 12 % errors).
 """
 import argparse
 import json
@@ -42,10 +45,13 @@ def main():
     ap.add_argument("--cpu-reads", type=int, default=1700)
     ap.add_argument("--bloom-bits", type=int, default=0, help="first filter bits per k-mer")
     ap.add_argument("--no-pipeline", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=("c2", "c4"))
     args = ap.parse_args()
     import synth
     import paper_2001_10049_amd as xd
-    w = synth.config("c2")
+    w = synth.config(args.workload)
+    if args.workload != "c2":
+        args.no_pipeline = True
     store = xd.ReadStore.from_workload(w)
     bb = args.bloom_bits
     first = xd.find_overlaps(store, k=K, m=M, bloom_bits=bb)
@@ -57,8 +63,11 @@ def main():
             "value": round(c["kmers"] / (ms / 1e3) / 1e6, 1), "unit": "M k-mers/s",
             "ms_per_step": round(ms, 3), "steps": args.steps, "warmup": args.warmup,
             "counts": c, "dtype": "u64 k-mer codes", "data": "synthetic",
-            "config": {"workload": "c2 read set: 13,743 reads, 138 Mbp, 30x of 4.6 Mbp, "
-                       "5/5/5 %% errors; k = %d, retained counts 2..%d" % (K, M),
+            "config": {"workload": ("c2 read set: 13,743 reads, 138 Mbp, 30x of 4.6 Mbp, "
+                                    "5/5/5 % errors" if args.workload == "c2" else
+                                    "c4 read set: 250,273 reads, 3.0 Gbp, 30x of 100 Mbp with "
+                                    "10 % repeats, 4/4/4 % errors") +
+                       "; k = %d, retained counts 2..%d" % (K, M),
                        "bloom_bits": bb or 16}}
     if args.cpu_reads:
         from oracle import overlap as oov

@@ -262,9 +262,11 @@ typedef struct {
  * from the filters; rounded up to a power of two, at least 4096; a table
  * that fills up is doubled and its pass rerun): speed/memory settings that
  * do not change the result.  Device
- * scratch is taken from the stream's memory pool: about bloom_bits/8 bytes
- * per k-mer for the filter plus (12 + 8 m) bytes per hash-table slot, the
- * table sized at twice the repeated occurrences.  Runs on hip_stream and
+ * scratch: about bloom_bits/8 bytes per k-mer for the filter, (12 + 8 m)
+ * bytes per hash-table slot (the table holds 1.5 times the repeated
+ * occurrences, rounded up to a power of two) and 32 bytes per seed; the
+ * buffers are kept for the next call on the device (see xd_release_memory),
+ * and calls on one device run one at a time.  Runs on hip_stream and
  * returns when done (the counts need host round trips).  More than 2^32 - 2
  * k-mers or seeds -> XD_EINVAL. */
 int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, uint32_t bloom_bits,
@@ -417,6 +419,15 @@ int xd_profile_read(xd_profile* out, int reset);
 
 /* Message for the calling thread's most recent failing call ("" if none). */
 const char* xd_last_error(void);
+
+/* Scratch memory: the calls that need device scratch (the batched form, the
+ * pair and traceback forms, candidate pairs) take it stream-ordered from a
+ * pool the library keeps per device, and freed scratch stays mapped for the
+ * next call; xd_find_overlaps keeps its own buffers per device between calls
+ * (it runs one call per device at a time), since mapping tens of GB again
+ * costs seconds.  This hands both back to the device; scratch of calls still
+ * running is kept.  XD_OK, or XD_EDEVICE. */
+int xd_release_memory(void);
 
 #ifdef __cplusplus
 }

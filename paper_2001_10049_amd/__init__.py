@@ -333,6 +333,12 @@ def workload_tensors(w, device="cuda"):
     return pairs, seeds, x
 
 
+def release_memory() -> None:
+    """Hands the library's cached scratch memory back to the device
+    (xd_release_memory)."""
+    _lib.check(_lib.load().xd_release_memory())
+
+
 def profile_enable(on: bool = True) -> None:
     """Start/stop per-kernel event timing of xd_align_batch calls."""
     _lib.check(_lib.load().xd_profile_enable(1 if on else 0))

@@ -28,6 +28,7 @@ EXPORTS = (
     "xd_plan_launch", "xd_plan_destroy", "xd_profile_enable", "xd_profile_read",
     "xd_server_request_bytes", "xd_server_fixed_bytes", "xd_server_create", "xd_server_submit", "xd_server_poll",
     "xd_server_cancel", "xd_server_stats", "xd_server_destroy", "xd_last_error",
+    "xd_release_memory",
 )
 
 
@@ -156,6 +157,8 @@ def load() -> ctypes.CDLL:
     lib.xd_profile_enable.restype = ctypes.c_int
     lib.xd_profile_read.argtypes = [ctypes.POINTER(Profile), ctypes.c_int]
     lib.xd_profile_read.restype = ctypes.c_int
+    lib.xd_release_memory.argtypes = []
+    lib.xd_release_memory.restype = ctypes.c_int
     lib.xd_last_error.argtypes = []
     lib.xd_last_error.restype = ctypes.c_char_p
     _lib = lib

@@ -20,6 +20,7 @@
 #include <stdint.h>
 #include <stdio.h>
 
+#include <mutex>
 #include <vector>
 
 #include "scan.h"
@@ -117,12 +118,13 @@ __device__ __forceinline__ void block_add(unsigned long long* dst, uint64_t v) {
   if (threadIdx.x == 0 && acc) atomicAdd(dst, acc);
 }
 
-// pass 1: filter A, repeats into filter B; ctr[0] += repeats
+// pass 1: filter A, repeats into filter B; ctr[0] += repeats, ctr[3] += the
+// repeats that set new bits in B (about one per distinct repeated k-mer)
 __global__ __launch_bounds__(kThreads) void k_bloom(KmerScan s, unsigned long long* A,
                                                     uint64_t WA, unsigned long long* B,
                                                     uint64_t WB, unsigned long long* ctr) {
   const uint64_t c = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-  uint32_t rep = 0;
+  uint32_t rep = 0, fresh = 0;
   if (c < s.n_chunks) {
     for_kmers(s, c, [&](uint32_t, uint32_t, uint64_t code) {
       const uint64_t h = fmix64(code);
@@ -130,12 +132,15 @@ __global__ __launch_bounds__(kThreads) void k_bloom(KmerScan s, unsigned long lo
       const unsigned long long old = atomicOr(&A[bloom_word(h, WA)], bits);
       if ((old & bits) == bits) {
         const uint64_t h2 = fmix64(code ^ kSaltB);
-        atomicOr(&B[bloom_word(h2, WB)], (unsigned long long)bloom_bits(h2));
+        const unsigned long long b2 = bloom_bits(h2);
+        const unsigned long long old2 = atomicOr(&B[bloom_word(h2, WB)], b2);
         ++rep;
+        fresh += (old2 & b2) != b2;
       }
     });
   }
   block_add(&ctr[0], rep);
+  block_add(&ctr[3], fresh);
 }
 
 // ctr[1] += set bits of B
@@ -367,6 +372,11 @@ __global__ __launch_bounds__(kThreads) void k_csr(const uint4* items, uint64_t n
 
 // ---- host ---------------------------------------------------------------------
 
+// the stage's device buffers, kept between calls (xd_release_memory frees them)
+constexpr int kMaxDevices = 64;
+std::mutex g_cache_mu[kMaxDevices];
+xscan::BlockCache g_cache[kMaxDevices];
+
 int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -420,6 +430,11 @@ extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, ui
                            "all be NULL");
   hipStream_t st = (hipStream_t)hip_stream;
   xd_overlap_counts cn = {};
+  // one call at a time per device: its buffers come from the device's cache
+  int dev = 0;
+  OV_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(XD_EINVAL, "xd_find_overlaps: device %d", dev);
+  std::lock_guard<std::mutex> call_lock(g_cache_mu[dev]);
 
   // chunks of kChunk k-mer starts, per read
   std::vector<uint64_t> chunk_off((size_t)sv.n_reads + 1);
@@ -437,7 +452,7 @@ extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, ui
     return fail(XD_EINVAL, "xd_find_overlaps: %llu k-mers (limit 2^32 - 2)",
                 (unsigned long long)cn.kmers);
 
-  Arena ar(st);
+  Arena ar(st, &g_cache[dev]);
   if (cn.kmers > 0) {
     const uint64_t WA = (cn.kmers * bloom_bits + 63) / 64;
     const uint64_t WB = WA / 16 + 64;
@@ -463,15 +478,18 @@ extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, ui
     cn.bloom_repeats = h_ctr[0];
     ar.drop(A);
 
-    // table size: the repeats bound the k-mers occurring twice or more; the
-    // singletons passing B are estimated from B's fill (three bits per key)
+    // table size: the repeats that set new bits in B count the k-mers
+    // occurring twice or more (fewer only where B's bits collide); the
+    // singletons passing B are estimated from B's fill (three bits per key);
+    // 1.5 times that keeps the expected load near 2/3, and a table that
+    // still fills up is regrown
     const double f = (double)h_ctr[1] / (64.0 * (double)WB);
-    const double expect = (double)h_ctr[0] + 2.0 * f * f * f * (double)cn.kmers;
+    const double expect = (double)h_ctr[3] + 2.0 * f * f * f * (double)cn.kmers;
     uint64_t cap = 4096;
     if (table_slots) {
       while (cap < table_slots && cap < (1ull << 32)) cap <<= 1;
     } else {
-      while ((double)cap < 2.0 * expect + 1024.0) cap <<= 1;
+      while ((double)cap < 1.5 * expect + 1024.0) cap <<= 1;
     }
 
     Table t{};
@@ -576,4 +594,17 @@ extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, ui
   if (le != hipSuccess) return hip_fail(le, "kernel launch");
   OV_TRY(hipStreamSynchronize(st));
   return XD_OK;
+}
+
+// frees the stage's kept buffers on every device (for xd_release_memory)
+__attribute__((visibility("hidden"))) void xd_internal_overlap_release() {
+  for (int d = 0; d < kMaxDevices; ++d) {
+    std::lock_guard<std::mutex> lk(g_cache_mu[d]);
+    if (g_cache[d].blocks.empty()) continue;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(d);
+    g_cache[d].release();
+    (void)hipSetDevice(cur);
+  }
 }

@@ -7,6 +7,8 @@
 
 #include <vector>
 
+#include "store_view.h"
+
 namespace {
 namespace xscan {
 
@@ -65,28 +67,81 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const T* in, T* out, uin
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) out[n] = run;
 }
 
-// stream-ordered scratch, released on the stream when it goes out of scope
+// Device blocks kept between calls of a synchronous entry point: only the
+// holder of its lock takes or gives blocks, and blocks come back only after
+// the holder's stream has drained.
+struct BlockCache {
+  std::vector<std::pair<void*, size_t>> blocks;
+  // the smallest kept block that holds bytes without wasting much of it
+  void* take(size_t bytes) {
+    size_t best = blocks.size();
+    for (size_t k = 0; k < blocks.size(); ++k) {
+      const size_t sz = blocks[k].second;
+      if (sz >= bytes && sz - bytes <= bytes + (64u << 20) &&
+          (best == blocks.size() || sz < blocks[best].second))
+        best = k;
+    }
+    if (best == blocks.size()) return nullptr;
+    void* p = blocks[best].first;
+    blocks.erase(blocks.begin() + best);
+    return p;
+  }
+  void give(void* p, size_t bytes) { blocks.emplace_back(p, bytes); }
+  void release() {
+    for (auto& b : blocks) (void)hipFree(b.first);
+    blocks.clear();
+  }
+};
+
+// scratch for one call: stream-ordered from the library pool, or, with a
+// cache, kept blocks (hipMalloc when none fits) that go back to the cache
 struct Arena {
   hipStream_t st;
-  std::vector<void*> held;
-  explicit Arena(hipStream_t s) : st(s) {}
+  BlockCache* cache;
+  struct Held {
+    void* p;
+    size_t bytes;
+  };
+  std::vector<Held> held;
+  explicit Arena(hipStream_t s, BlockCache* c = nullptr) : st(s), cache(c) {}
   ~Arena() {
-    for (void* p : held)
-      if (p) (void)hipFreeAsync(p, st);
+    if (cache) (void)hipStreamSynchronize(st);
+    for (auto& h : held) put_back(h);
+  }
+  void put_back(Held& h) {
+    if (!h.p) return;
+    if (cache) cache->give(h.p, h.bytes);
+    else (void)hipFreeAsync(h.p, st);
+    h.p = nullptr;
   }
   template <typename T>
   hipError_t get(T** p, uint64_t count) {
     *p = nullptr;
-    hipError_t e = hipMallocAsync((void**)p, (count ? count : 1) * sizeof(T), st);
-    if (e == hipSuccess) held.push_back(*p);
-    return e;
-  }
-  void drop(void* p) {
-    for (auto& q : held)
-      if (q == p) {
-        (void)hipFreeAsync(q, st);
-        q = nullptr;
+    const size_t bytes = (count ? count : 1) * sizeof(T);
+    void* q = nullptr;
+    hipError_t e = hipSuccess;
+    if (cache) {
+      q = cache->take(bytes);
+      if (!q) {
+        e = hipMalloc(&q, bytes);
+        if (e == hipErrorOutOfMemory) {  // hand back what the cache keeps and retry
+          (void)hipGetLastError();
+          cache->release();
+          e = hipMalloc(&q, bytes);
+        }
       }
+    } else {
+      e = xd_internal_malloc_async(&q, bytes, st);
+    }
+    if (e != hipSuccess) return e;
+    held.push_back({q, bytes});
+    *p = (T*)q;
+    return hipSuccess;
+  }
+  // the block may serve a later get() of this call: same stream, so ordered
+  void drop(void* p) {
+    for (auto& h : held)
+      if (h.p == p) put_back(h);
   }
 };
 

@@ -19,3 +19,10 @@ struct StoreView {
 int xd_internal_store_view(const xd_store* s, StoreView* v);
 // records msg as the calling thread's last error and returns code
 int xd_internal_fail(int code, const char* msg);
+// stream-ordered scratch from the library's pool on the current device; the
+// pool keeps freed memory mapped for the next call (xd_release_memory hands
+// it back).  Free with hipFreeAsync.
+#include <hip/hip_runtime.h>
+hipError_t xd_internal_malloc_async(void** p, size_t bytes, hipStream_t st);
+// frees the buffers xd_find_overlaps keeps between calls
+void xd_internal_overlap_release();

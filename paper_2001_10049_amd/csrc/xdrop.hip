@@ -1093,7 +1093,7 @@ int batch_async(const BatchArgs& A, uint32_t max_len, bool persistent, const Tun
                 hipStream_t stream) {
   const BandGeom g = band_geom(max_len, (uint32_t)tu.band_blocks);
   char* mem = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&mem, scratch_bytes(A.n, g), stream));
+  HIP_TRY(xd_internal_malloc_async((void**)&mem, scratch_bytes(A.n, g), stream));
   int rc = enqueue(A, scratch_carve(mem, A.n, g), persistent, tu, stream, true);
   hipError_t fe = hipFreeAsync(mem, stream);
   if (rc) return rc;
@@ -1102,6 +1102,13 @@ int batch_async(const BatchArgs& A, uint32_t max_len, bool persistent, const Tun
 }
 
 }  // namespace
+
+// the library's stream-ordered pools, one per device, created on first use;
+// they keep freed scratch mapped (mapping tens of GB again on every call
+// costs seconds)
+std::mutex g_pool_mu;
+constexpr int kMaxDevices = 64;
+hipMemPool_t g_pools[kMaxDevices] = {};
 
 // for the other translation units of the library (not exported)
 __attribute__((visibility("hidden"))) int xd_internal_fail(int code, const char* msg) {
@@ -1122,6 +1129,37 @@ __attribute__((visibility("hidden"))) int xd_internal_store_view(const xd_store*
   return XD_OK;
 }
 
+__attribute__((visibility("hidden"))) hipError_t xd_internal_malloc_async(void** p, size_t bytes,
+                                                                        hipStream_t st) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipMallocAsync(p, bytes, st);
+  hipMemPool_t pool = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!g_pools[dev]) {
+      hipMemPoolProps props = {};
+      props.allocType = hipMemAllocationTypePinned;
+      props.handleTypes = hipMemHandleTypeNone;
+      props.location.type = hipMemLocationTypeDevice;
+      props.location.id = dev;
+      hipMemPool_t np = nullptr;
+      e = hipMemPoolCreate(&np, &props);
+      if (e != hipSuccess) return e;
+      uint64_t keep = UINT64_MAX;
+      e = hipMemPoolSetAttribute(np, hipMemPoolAttrReleaseThreshold, &keep);
+      if (e != hipSuccess) {
+        (void)hipMemPoolDestroy(np);
+        return e;
+      }
+      g_pools[dev] = np;
+    }
+    pool = g_pools[dev];
+  }
+  return hipMallocFromPoolAsync(p, bytes, pool, st);
+}
+
 // device bytes of the band tier's rows for a store whose longest read has
 // max_len bases, with `blocks` workgroups (0 = the default count)
 __attribute__((visibility("hidden"))) uint64_t xd_internal_band_bytes(uint32_t max_len,
@@ -1132,6 +1170,17 @@ __attribute__((visibility("hidden"))) uint64_t xd_internal_band_bytes(uint32_t m
 extern "C" {
 
 const char* xd_last_error(void) { return g_err.c_str(); }
+
+int xd_release_memory(void) {
+  xd_internal_overlap_release();
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  for (int d = 0; d < kMaxDevices; ++d) {
+    if (!g_pools[d]) continue;
+    hipError_t e = hipMemPoolTrimTo(g_pools[d], 0);
+    if (e != hipSuccess) return hip_fail(e, "hipMemPoolTrimTo");
+  }
+  return XD_OK;
+}
 
 int xd_pack_reads(const uint8_t* codes, const uint64_t* off, const uint32_t* len,
                   uint32_t n_reads, uint32_t* words, uint64_t* word_off, uint64_t* n_words) {
@@ -1302,7 +1351,7 @@ int xd_align_pairs(const xd_store* store, uint64_t n_pairs, const uint32_t* pair
                               al(4 * S) + al(8 * S);
   const uint64_t batch_bytes = S ? scratch_bytes(S, g) : 0;
   char* mem = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&mem, task_bytes + batch_bytes + 256, stream));
+  HIP_TRY(xd_internal_malloc_async((void**)&mem, task_bytes + batch_bytes + 256, stream));
   char* q = mem;
   auto take = [&](uint64_t b) {
     char* r = q;

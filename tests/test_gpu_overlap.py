@@ -167,3 +167,14 @@ def test_pairs_feed_alignment():
                 assert np.array_equal(out[f].cpu().numpy()[idx], ref[f]), (max_seeds, f)
             assert np.array_equal(out["cells"].cpu().numpy()[idx].astype(np.uint64),
                                   ref["cells"].astype(np.uint64))
+
+
+def test_release_memory_between_calls():
+    # scratch stays cached in the library's pool between calls; handing it
+    # back changes nothing for the next call
+    w = synth.config("c2-small")
+    first = gpu(w.codes, w.off, w.length, 17, 8)
+    xd.release_memory()
+    again = gpu(w.codes, w.off, w.length, 17, 8)
+    for a, b in zip(first[:3], again[:3]):
+        assert np.array_equal(a, b)
