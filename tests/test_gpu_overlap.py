@@ -178,3 +178,35 @@ def test_release_memory_between_calls():
     again = gpu(w.codes, w.off, w.length, 17, 8)
     for a, b in zip(first[:3], again[:3]):
         assert np.array_equal(a, b)
+
+
+def test_c2_candidates_align_like_the_oracle():
+    # the pipeline at full size, as bench_overlap.py runs it: every candidate
+    # pair of the c2 read set aligned from its first seed (chance pairs
+    # included, whose extensions reach the wide windows); a sample of pairs,
+    # half of them single-seed pairs (mostly chance collisions), against the
+    # pair oracle
+    w = synth.config("c2")
+    with xd.ReadStore.from_workload(w) as st:
+        r = xd.find_overlaps(st, k=17, m=8)
+        out = xd.align_pairs(st, r["pairs"], r["seed_off"], r["seeds"], x_scalar=25,
+                             min_dist=17, max_seeds=1, k=17, n_seeds=r["counts"]["seeds"])
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        so = r["seed_off"].cpu().numpy()
+        pairs_h = r["pairs"].cpu().numpy()
+        seeds_h = r["seeds"].cpu().numpy()
+    assert (got["status"] == 0).all()
+    rng = np.random.default_rng(4)
+    single = np.nonzero(so[1:] - so[:-1] == 1)[0]
+    idx = np.concatenate([rng.choice(single, 15, replace=False),
+                          rng.choice(pairs_h.shape[0], 15, replace=False)])
+    sub_off = np.concatenate([[0], np.cumsum(so[idx + 1] - so[idx])]).astype(np.uint64)
+    sub_seeds = np.concatenate([seeds_h[so[i]:so[i + 1]] for i in idx])
+    ref = opairs.align_pairs(w.codes, w.off, w.length, pairs_h[idx], sub_off, sub_seeds,
+                             x_scalar=25, min_dist=17, max_seeds=1, k=17)
+    for f in ("score", "status", "seed_idx", "n_kept"):
+        assert np.array_equal(got[f][idx], ref[f]), f
+    for f in ("beg", "end"):
+        assert np.array_equal(got[f][idx].view(np.uint32), ref[f].astype(np.uint32)), f
+    assert np.array_equal(got["cells"][idx].astype(np.uint64), ref["cells"].astype(np.uint64))
