@@ -227,7 +227,10 @@ def find_overlaps(store: ReadStore, k=17, m=8, bloom_bits=0, capacity=None, stre
     """Candidate read pairs sharing a retained k-mer (xd_find_overlaps).
 
     capacity: (max_pairs, max_seeds) to allocate at once; None asks the
-    library for the counts first (one extra run).  Returns dict(pairs int32
+    library for the counts first (one extra run).  bloom_bits and
+    table_slots size the first filter and the first hash table (0: the
+    library's choice); they change speed and memory, never the result.
+    Returns dict(pairs int32
     [P, 2], seed_off int64 [P + 1], seeds int32 [S, 2] device tensors, counts
     dict) or raises XdropError(XD_EAGAIN) when capacity is too small."""
     import torch
