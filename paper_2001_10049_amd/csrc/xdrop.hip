@@ -292,6 +292,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_ext_tier(const TierArgs* __restr
     const uint32_t seg_lo = Q.seg ? __builtin_amdgcn_readfirstlane(Q.seg[0]) : 0u;
     const uint32_t seg_len = Q.seg ? __builtin_amdgcn_readfirstlane(Q.seg[1]) - seg_lo : 0u;
     const uint32_t n_in = Q.in_count ? __builtin_amdgcn_readfirstlane(*Q.in_count) : 0u;
+    if (seg_len + n_in == 0) break;  // no work: leave without touching the shared head
     uint32_t idx = 0;
     if (xd::lane_id() == 0) idx = atomicAdd(Q.head, 1u);
     idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
