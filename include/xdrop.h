@@ -114,9 +114,10 @@ int xd_store_info(const xd_store* store, uint64_t* device_bytes, uint32_t* n_rea
  *   cells  uint64[n]   out, may be NULL; evaluated cells, 0 when status != 0
  * hip_stream: a hipStream_t (NULL = the default stream).  The call is
  * asynchronous: it validates the scalar arguments, enqueues kernels and a
- * stream-ordered scratch allocation, and returns.  The scratch is about 90
- * bytes per task plus the band tier's rows (xd_tuning.band_blocks; at most
- * 64 MiB by default).  k >= 1.  n = 0 is a no-op.
+ * stream-ordered scratch allocation, and returns.  The scratch size is
+ * xd_batch_scratch_bytes(store, n, NULL): about 96 bytes per task plus the
+ * band tier's rows (xd_tuning.band_blocks; at most 64 MiB by default).
+ * k >= 1.  n = 0 is a no-op.
  * Invalid scalars (k, scores, x_scalar when x == NULL) -> XD_EINVAL, nothing
  * enqueued. */
 int xd_align_batch(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,
@@ -141,6 +142,16 @@ typedef struct {
                            of the store + 64) bytes or so of scratch.  0 = as many as fit in
                            64 MiB, at most 16 */
 } xd_tuning;
+
+/* Device scratch bytes of one xd_align_batch / xd_align_batch_persistent call
+ * of n tasks (what the call takes from the library's stream-ordered pool):
+ * per task, two 24-byte extension results and six 4-byte-per-extension queue
+ * and overflow lists, each array rounded up to 256 bytes, plus 3,840 bytes of
+ * counters and tier arguments; with a store, also the band tier's rows for
+ * its longest read (tuning->band_blocks workgroups; tuning may be NULL).
+ * store = NULL leaves the rows out.  Host arithmetic only.  0 for an invalid
+ * tuning. */
+uint64_t xd_batch_scratch_bytes(const xd_store* store, uint64_t n, const xd_tuning* tuning);
 
 /* Same contract and results as xd_align_batch.  Extensions are ordered on
  * the device longest-first (a histogram of estimated antidiagonal counts and
@@ -243,7 +254,7 @@ typedef struct {
 /* Candidate read pairs (paper section 4 stages 1-3; sections 6-8): the reads
  * of the store are cut into their k-mers (every start p with p + k <= length,
  * forward strand); a k-mer occurring 2..m times over all reads is retained
- * (singletons and k-mers above the frequency bound m are dropped, section 3),
+ * (singletons and k-mers above the frequency bound m are dropped, section 2),
  * and every two occurrences of a retained k-mer in different reads ra < rb,
  * at pa in ra and pb in rb, form the seed (pa, pb) of the pair (ra, rb)
  * (Alg. 1).  Output, device pointers, caller-owned:
@@ -356,7 +367,10 @@ typedef struct {
   uint64_t inflight_bytes;          /* admitted device bytes now */
 } xd_server_counters;
 
-/* Device bytes a request of n tasks holds while in flight. */
+/* Device bytes a request of n tasks is charged while in flight: its task and
+ * result buffer (52 bytes per task, rounded up to 256) plus
+ * xd_batch_scratch_bytes(NULL, n, NULL), as if it ran alone.  A batch packing
+ * several requests uses no more than the sum of their charges. */
 uint64_t xd_server_request_bytes(uint64_t n);
 
 /* Device bytes a server on this store holds whatever its load: each slot's

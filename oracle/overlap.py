@@ -1,7 +1,7 @@
 """Candidate read pairs from shared retained k-mers: TEST INFRASTRUCTURE ONLY
 (see oracle/__init__.py).
 
-Section 3 of the paper drops k-mers that occur once across the reads
+Section 2 of the paper drops k-mers that occur once across the reads
 (singletons) and those occurring more than m times (likely repeats); the rest
 are the retained k-mers.  Section 8 (Alg. 1) pairs every two entries of each
 retained k-mer's list of (read, position) occurrences into an alignment task.

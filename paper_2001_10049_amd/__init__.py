@@ -354,6 +354,14 @@ def profile_read(reset: bool = True) -> dict:
     return {f: getattr(p, f) for f, _ in _lib.Profile._fields_}
 
 
+def batch_scratch_bytes(n: int, store=None, tuning=None) -> int:
+    """Device scratch bytes of one batch call of n tasks (xd_batch_scratch_bytes);
+    without a store the band tier's rows are left out."""
+    t = _tuning_struct(tuning)
+    return int(_lib.load().xd_batch_scratch_bytes(store.handle if store is not None else None,
+                                                  int(n), ctypes.byref(t)))
+
+
 def request_bytes(n: int) -> int:
     """Device bytes a server request of n tasks holds while in flight."""
     return int(_lib.load().xd_server_request_bytes(int(n)))

@@ -22,7 +22,8 @@ OVERLAP_M_MAX = 64
 # every symbol include/xdrop.h declares
 EXPORTS = (
     "xd_pack_reads", "xd_store_create", "xd_store_create_from_codes", "xd_store_destroy",
-    "xd_store_info", "xd_align_batch", "xd_align_batch_persistent", "xd_align_pairs",
+    "xd_store_info", "xd_align_batch", "xd_batch_scratch_bytes", "xd_align_batch_persistent",
+    "xd_align_pairs",
     "xd_banded_batch", "xd_banded_traceback", "xd_find_overlaps",
     "xd_plan_create",
     "xd_plan_launch", "xd_plan_destroy", "xd_profile_enable", "xd_profile_read",
@@ -137,6 +138,8 @@ def load() -> ctypes.CDLL:
     lib.xd_plan_launch.restype = ctypes.c_int
     lib.xd_plan_destroy.argtypes = [vp]
     lib.xd_plan_destroy.restype = None
+    lib.xd_batch_scratch_bytes.argtypes = [vp, u64, ctypes.POINTER(Tuning)]
+    lib.xd_batch_scratch_bytes.restype = u64
     lib.xd_server_request_bytes.argtypes = [u64]
     lib.xd_server_request_bytes.restype = u64
     lib.xd_server_fixed_bytes.argtypes = [vp, ctypes.POINTER(ServerConfig)]

@@ -34,11 +34,10 @@ double now_s() {
 }
 
 // per task: pairs 8 + seeds 8 + x 4 in, score 4 + beg 8 + end 8 + status 4 +
-// cells 8 out; the batched form's scratch: 2 extensions x (24 + 5 lists x 4)
-// bytes; per batch the counters and tier arguments (the band tier's rows are
-// held per slot, outside the requests' share of the budget)
-constexpr uint64_t kInBytes = 20, kOutBytes = 32, kScratchPerTask = 88;
-constexpr uint64_t kBatchFixedBytes = 8192;
+// cells 8 out, in one device buffer per batch; the batched form's own scratch
+// is what xd_batch_scratch_bytes reports (the band tier's rows are held per
+// slot, outside the requests' share of the budget)
+constexpr uint64_t kInBytes = 20, kOutBytes = 32;
 
 struct Req {
   uint64_t id = 0, n = 0, bytes = 0, batch = 0;
@@ -70,6 +69,8 @@ struct Slot {
 
 // the library's error slot (xdrop.hip): xd_last_error() reports it
 int xd_internal_fail(int code, const char* msg);
+// the batch calls' check of k and the scores (sets the message)
+int xd_internal_check_scoring(int32_t k, int32_t match, int32_t mismatch, int32_t gap);
 uint64_t xd_internal_band_bytes(uint32_t max_len, uint32_t blocks);
 
 struct xd_server {
@@ -178,20 +179,36 @@ int launch_slot(xd_server* S, Slot& sl, const std::vector<xd::AdmissionItem>& b)
   const uint32_t* d_seeds = d_pairs + 2 * n;
   const int32_t* d_x = (const int32_t*)(d_seeds + 2 * n);
   char* o = d + n * kInBytes;
+  // on a failure below, the device buffer goes back to the pool (stream
+  // ordered, after whatever was enqueued) before the batch is failed
+  auto drop_buf = [&]() {
+    (void)hipFreeAsync(sl.d_buf, s);
+    sl.d_buf = nullptr;
+  };
   e = hipEventRecord(sl.start, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d, sl.h_buf, n * kInBytes, hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return set_err(XD_EDEVICE, "server: upload failed");
+  if (e != hipSuccess) {
+    drop_buf();
+    return set_err(XD_EDEVICE, "server: upload failed");
+  }
   int rc = xd_align_batch_persistent(S->store, d_pairs, d_seeds, d_x, 0, n, S->cfg.k,
                                      S->cfg.match, S->cfg.mismatch, S->cfg.gap, (int32_t*)o,
                                      (uint32_t*)(o + 4 * n), (uint32_t*)(o + 12 * n),
                                      (int32_t*)(o + 20 * n), (uint64_t*)(o + 24 * n),
                                      &S->cfg.tuning, s);
-  if (rc) return rc;  // the batch call has set the message
+  if (rc) {  // the batch call has set the message
+    drop_buf();
+    return rc;
+  }
   e = hipMemcpyAsync(sl.h_buf + n * kInBytes, o, n * kOutBytes, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipFreeAsync(sl.d_buf, s);
+  if (e != hipSuccess) {
+    drop_buf();
+    return set_err(XD_EDEVICE, "server: download failed");
+  }
+  e = hipFreeAsync(sl.d_buf, s);
+  sl.d_buf = nullptr;
   if (e == hipSuccess) e = hipEventRecord(sl.done, s);
   if (e != hipSuccess) return set_err(XD_EDEVICE, "server: download failed");
-  sl.d_buf = nullptr;
   sl.busy = true;
   sl.t_start = t;
   S->st.batches += 1;
@@ -254,8 +271,13 @@ void worker_main(xd_server* S) {
 
 extern "C" {
 
+// A request is charged as if it ran alone: its in/out buffer and the whole
+// scratch of a batch of n tasks, fixed part included.  A batch packing
+// several requests uses at most the sum of their charges (each array's
+// rounding and the fixed part are paid once per batch, not per request).
 uint64_t xd_server_request_bytes(uint64_t n) {
-  return n * (kInBytes + kOutBytes + kScratchPerTask) + kBatchFixedBytes;
+  return ((n * (kInBytes + kOutBytes) + 255) & ~255ull) + xd_batch_scratch_bytes(nullptr, n,
+                                                                                   nullptr);
 }
 
 uint64_t xd_server_fixed_bytes(const xd_store* store, const xd_server_config* cfg) {
@@ -268,8 +290,12 @@ uint64_t xd_server_fixed_bytes(const xd_store* store, const xd_server_config* cf
 }
 
 int xd_server_create(const xd_store* store, const xd_server_config* cfg, xd_server** out) {
-  if (!out || !store || !cfg) return set_err(XD_EINVAL, "xd_server_create: null argument");
+  if (!out || !cfg) return set_err(XD_EINVAL, "xd_server_create: null argument");
   *out = nullptr;
+  // the batches would all fail: refuse the scheme here
+  const int sc = xd_internal_check_scoring(cfg->k, cfg->match, cfg->mismatch, cfg->gap);
+  if (sc) return sc;
+  if (!store) return set_err(XD_EINVAL, "xd_server_create: null store");
   xd_server* S = new xd_server();
   S->store = store;
   S->cfg = *cfg;
@@ -283,12 +309,12 @@ int xd_server_create(const xd_store* store, const xd_server_config* cfg, xd_serv
     return set_err(XD_EINVAL, "xd_server_create: at most 64 slots");
   }
   const uint64_t fixed = xd_server_fixed_bytes(store, &S->cfg);
-  if (S->cfg.hbm_budget_bytes <= fixed + kBatchFixedBytes) {
+  if (S->cfg.hbm_budget_bytes <= fixed + xd_server_request_bytes(1)) {
     delete S;
     char msg[128];
     snprintf(msg, sizeof(msg),
              "xd_server_create: hbm_budget_bytes must exceed the fixed %llu bytes",
-             (unsigned long long)(fixed + kBatchFixedBytes));
+             (unsigned long long)(fixed + xd_server_request_bytes(1)));
     return set_err(XD_EINVAL, msg);
   }
   S->adm = new xd::AdmissionQueue(S->cfg.hbm_budget_bytes - fixed, S->cfg.slots,

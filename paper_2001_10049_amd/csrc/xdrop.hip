@@ -114,11 +114,16 @@ constexpr int kCtrWords = 32;
 constexpr int kTierArgsBytes = 6 * 256;  // >= 6 * sizeof(TierArgs), checked below
 constexpr uint64_t kFixedBytes = (kBins * 4 + kCtrWords * 4 + kTierArgsBytes + 255) & ~255ull;
 
-uint64_t scratch_bytes(uint64_t n, const BandGeom& g) {
+// scratch of a batch of n tasks without the band tier's rows
+uint64_t task_scratch_bytes(uint64_t n) {
   const uint64_t n_ext = 2 * n;
   const uint64_t ext = (n_ext * sizeof(ExtOut) + 255) & ~255ull;
   const uint64_t list = (n_ext * 4 + 255) & ~255ull;
-  return ext + 6 * list + kFixedBytes + band_bytes(g);
+  return ext + 6 * list + kFixedBytes;
+}
+
+uint64_t scratch_bytes(uint64_t n, const BandGeom& g) {
+  return task_scratch_bytes(n) + band_bytes(g);
 }
 
 Scratch scratch_carve(char* base, uint64_t n, const BandGeom& g) {
@@ -1161,6 +1166,12 @@ __attribute__((visibility("hidden"))) hipError_t xd_internal_malloc_async(void**
   return hipMallocFromPoolAsync(p, bytes, pool, st);
 }
 
+__attribute__((visibility("hidden"))) int xd_internal_check_scoring(int32_t k, int32_t match,
+                                                                    int32_t mismatch,
+                                                                    int32_t gap) {
+  return check_scoring(k, match, mismatch, gap);
+}
+
 // device bytes of the band tier's rows for a store whose longest read has
 // max_len bases, with `blocks` workgroups (0 = the default count)
 __attribute__((visibility("hidden"))) uint64_t xd_internal_band_bytes(uint32_t max_len,
@@ -1171,6 +1182,14 @@ __attribute__((visibility("hidden"))) uint64_t xd_internal_band_bytes(uint32_t m
 extern "C" {
 
 const char* xd_last_error(void) { return g_err.c_str(); }
+
+uint64_t xd_batch_scratch_bytes(const xd_store* store, uint64_t n, const xd_tuning* tuning) {
+  const uint64_t per_task = task_scratch_bytes(n);
+  if (!store) return per_task;
+  Tuned tu;
+  if (check_tuning(tuning, tu) != XD_OK) return 0;
+  return per_task + band_bytes(band_geom(store->max_len, (uint32_t)tu.band_blocks));
+}
 
 int xd_release_memory(void) {
   xd_internal_overlap_release();

@@ -131,3 +131,44 @@ def test_banded_traceback_argument_errors_without_device():
     assert call(dummy, n=1) == _lib.XD_EINVAL          # null task and result arrays
     assert call(dummy, n=(1 << 30) + 1) == _lib.XD_EINVAL
     assert call(dummy, n=0) == _lib.XD_OK              # nothing to do
+
+
+def _al(b):
+    return (b + 255) // 256 * 256
+
+
+def test_batch_scratch_bytes_layout():
+    # per task two 24-byte extension results and six 4-byte lists per
+    # extension, each array rounded up to 256 bytes, plus 3,840 fixed bytes
+    lib = _lib.load()
+    for n in (0, 1, 2, 5, 31, 32, 33, 1000, 12345, 10**6):
+        want = _al(48 * n) + 6 * _al(8 * n) + 3840
+        assert lib.xd_batch_scratch_bytes(None, n, None) == want, n
+    bad = _lib.Tuning(3, 0, 0, 0, 0, 0)  # waves_per_cu must be a multiple of 4
+    assert lib.xd_batch_scratch_bytes(ctypes.c_void_p(1), 10, ctypes.byref(bad)) == 0
+
+
+def test_server_request_bytes_cover_the_batch():
+    # a request is charged at least its in/out buffer plus the whole batch
+    # scratch of a batch of its size; several requests packed together are
+    # charged at least what their batch takes
+    lib = _lib.load()
+    for n in range(1, 10001):
+        need = 52 * n + lib.xd_batch_scratch_bytes(None, n, None)
+        assert lib.xd_server_request_bytes(n) >= need, n
+    sizes = [1, 7, 300, 1000, 4096, 9999]
+    packed = sum(sizes)
+    assert sum(lib.xd_server_request_bytes(s) for s in sizes) >= (
+        _al(52 * packed) + lib.xd_batch_scratch_bytes(None, packed, None))
+
+
+def test_server_create_rejects_bad_scoring():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    for k, m, mm, g in [(0, 1, -1, -1), (17, 0, -1, -1), (17, 1, 1, -1), (17, 1, -1, 0)]:
+        cfg = _lib.ServerConfig(1 << 30, 1, 0, 0, k, m, mm, g, _lib.Tuning())
+        # the dummy store is never dereferenced: the scheme is checked first
+        rc = lib.xd_server_create(ctypes.c_void_p(1), ctypes.byref(cfg), ctypes.byref(h))
+        assert rc == _lib.XD_EINVAL and not h.value, (k, m, mm, g)
+        msg = lib.xd_last_error()
+        assert b"k must" in msg or b"match" in msg or b"mismatch" in msg or b"gap" in msg

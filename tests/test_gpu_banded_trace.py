@@ -97,6 +97,25 @@ def test_trace_edges_and_statuses():
     assert_same(gpu_trace(w, ws), ref, "edges")
 
 
+@pytest.mark.parametrize("a,b,wdt,scheme,cig", [
+    ("ACGTTACG", "ACGTACG", 3, (1, -1, -1), "3M1D4M"),    # diagonal before (i-1, j)
+    ("ACGTACG", "ACGTTACG", 3, (1, -1, -1), "3M1I4M"),    # diagonal before (i, j-1)
+    ("ACGTAGGGG", "ACGTCGGGG", 4, (1, -3, -1), "4M1I1D4M"),  # (i-1, j) before (i, j-1)
+])
+def test_trace_tie_rule_cases(a, b, wdt, scheme, cig):
+    # the oracle's hand-worked tie cases, on the GPU (seed (0, 0): band around
+    # the main diagonal)
+    code = {c: q for q, c in enumerate("ACGT")}
+    reads = [np.array([code[c] for c in r], np.uint8) for r in (a, b)]
+    w = workload_from(reads, [(0, 1, 0, 0, 0)], k=1)
+    ws = np.array([wdt], np.int32)
+    got = gpu_trace(w, ws, scheme)
+    ref = oracle_trace(w, ws, scheme)
+    assert_same(got, ref, "tie case %s/%s" % (a, b))
+    ops = got["ops"][0, :got["n_ops"][0]].view(np.uint32)
+    assert "".join("%d%s" % (e >> 2, "MID"[e & 3]) for e in ops) == cig
+
+
 @pytest.mark.parametrize("scheme", [(2, -3, -2), (5, -4, -7)])
 def test_trace_scoring(scheme):
     w = synth.config("c1-small")
