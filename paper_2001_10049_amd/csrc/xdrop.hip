@@ -43,6 +43,7 @@ using xd::ExtOut;
 namespace {
 
 constexpr uint32_t kWideBlocks = 2048;
+constexpr uint64_t kChunkBlocks = 1ull << 24;  // one-wave blocks per launch of a per-item grid
 constexpr int kCostBins = 128;          // per tier
 constexpr int kBins = 4 * kCostBins;    // tier-major
 constexpr int kBandWaves = 16;          // waves per band-tier workgroup
@@ -270,10 +271,10 @@ __global__ __launch_bounds__(256) void k_reset(uint32_t* ctr, uint32_t* hist, Ti
 }
 
 template <int CPL, int GS, bool UNIT>
-__global__ __launch_bounds__(64) void k_ext_first(BatchArgs A, uint32_t* ovf_list,
+__global__ __launch_bounds__(64) void k_ext_first(BatchArgs A, uint32_t e0, uint32_t* ovf_list,
                                                   uint32_t* ovf_count) {
   __shared__ uint32_t ring[xd::Tier<CPL, GS>::LDS_WORDS];
-  const uint32_t e = blockIdx.x;
+  const uint32_t e = e0 + blockIdx.x;
   if (!run_ext<CPL, GS, UNIT>(A, e, ring)) push_list(ovf_list, ovf_count, e);
 }
 
@@ -879,8 +880,12 @@ void launch_wide(const Scratch& S, uint32_t blocks, hipStream_t stream) {
 template <bool UNIT>
 void launch_plain_ext(const BatchArgs& A, const Scratch& S, uint64_t n_ext, hipEvent_t* ev,
                       hipStream_t stream) {
-  hipLaunchKernelGGL((k_ext_first<1, 16, UNIT>), dim3((uint32_t)n_ext), dim3(64), 0, stream, A,
-                     S.ovf[0], S.ctr + kOvfCount + 0);
+  // a grid holds at most 2^32 - 1 work-items: launch in chunks of 2^24 waves
+  for (uint64_t e0 = 0; e0 < n_ext; e0 += kChunkBlocks) {
+    const uint64_t nb = std::min<uint64_t>(kChunkBlocks, n_ext - e0);
+    hipLaunchKernelGGL((k_ext_first<1, 16, UNIT>), dim3((uint32_t)nb), dim3(64), 0, stream, A,
+                       (uint32_t)e0, S.ovf[0], S.ctr + kOvfCount + 0);
+  }
   if (ev) (void)hipEventRecord(ev[1], stream);
   launch_wide<UNIT>(S, kWideBlocks / 4, stream);
   if (ev) (void)hipEventRecord(ev[2], stream);
@@ -1462,10 +1467,15 @@ int xd_banded_batch(const xd_store* store, const uint32_t* pairs, const uint32_t
   A.tr_off = nullptr;
   A.tr_off0 = 0;
   hipStream_t stream = (hipStream_t)hip_stream;
-  if (match == 1)
-    hipLaunchKernelGGL((k_banded<true, false>), dim3((uint32_t)n), dim3(64), 0, stream, A);
-  else
-    hipLaunchKernelGGL((k_banded<false, false>), dim3((uint32_t)n), dim3(64), 0, stream, A);
+  // one wave per task, in chunks of 2^24 (a grid holds at most 2^32 - 1 work-items)
+  for (uint64_t t0 = 0; t0 < n; t0 += kChunkBlocks) {
+    A.t0 = (uint32_t)t0;
+    const uint32_t nb = (uint32_t)std::min<uint64_t>(kChunkBlocks, n - t0);
+    if (match == 1)
+      hipLaunchKernelGGL((k_banded<true, false>), dim3(nb), dim3(64), 0, stream, A);
+    else
+      hipLaunchKernelGGL((k_banded<false, false>), dim3(nb), dim3(64), 0, stream, A);
+  }
   hipError_t le = hipGetLastError();
   if (le != hipSuccess) return hip_fail(le, "kernel launch");
   return XD_OK;
@@ -1522,7 +1532,7 @@ int xd_banded_traceback(const xd_store* store, const uint32_t* pairs, const uint
   A.tr_off = off;
   for (uint64_t t0 = 0; t0 < n;) {
     uint64_t t1 = t0 + 1;
-    while (t1 < n && h[t1 + 1] - h[t0] <= cap) ++t1;
+    while (t1 < n && t1 - t0 < kChunkBlocks && h[t1 + 1] - h[t0] <= cap) ++t1;
     A.t0 = (uint32_t)t0;
     A.tr_off0 = h[t0];
     if (match == 1)
