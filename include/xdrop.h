@@ -125,6 +125,25 @@ int xd_align_batch(const xd_store* store, const uint32_t* pairs, const uint32_t*
                    int32_t mismatch, int32_t gap, int32_t* score, uint32_t* beg, uint32_t* end,
                    int32_t* status, uint64_t* cells, void* hip_stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): xd_align_batch without any
+ * allocation.  Same arguments, results and asynchrony; its scratch is a fixed
+ * device array of XD_NOALLOC_SCRATCH_BYTES in the library, one per device,
+ * held until the process ends (the band tier runs one workgroup).  A batch
+ * whose xd_batch_scratch_bytes(store, n, &{band_blocks = 1}) exceeds that
+ * size returns XD_EINVAL with nothing enqueued.  Every call on a device uses
+ * the same array: calls that overlap on one device (other streams, other
+ * threads, or a second call before the first one's work has completed on a
+ * different stream) race and give undefined results; calls on one stream are
+ * ordered and safe.  The array keeps the last call's contents; each call
+ * clears what it needs cleared on the device.  No profiling records. */
+#define XD_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int xd_align_batch_noalloc(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,
+                           const int32_t* x, int32_t x_scalar, uint64_t n, int32_t k,
+                           int32_t match, int32_t mismatch, int32_t gap, int32_t* score,
+                           uint32_t* beg, uint32_t* end, int32_t* status, uint64_t* cells,
+                           void* hip_stream);
+
 /* ---- batched form: longest-first device queue, persistent waves ---------- */
 
 /* Tunables of the batched form (all 0 = default).  An autotuner picks them per

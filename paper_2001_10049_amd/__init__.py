@@ -144,9 +144,12 @@ def _check_batch(pairs, seeds, x, out):
 
 
 def align_batch(store: ReadStore, pairs, seeds, x=None, x_scalar=0, k=17, match=1,
-                mismatch=-1, gap=-1, out=None, stream=None, persistent=False, tuning=None):
+                mismatch=-1, gap=-1, out=None, stream=None, persistent=False, tuning=None,
+                noalloc=False):
     """Aligns n tasks on the GPU (xd_align_batch, or the batched form
-    xd_align_batch_persistent when persistent=True).
+    xd_align_batch_persistent when persistent=True, or xd_align_batch_noalloc,
+    which takes no memory, when noalloc=True; pass `out` then to allocate
+    nothing on the Python side either).
 
     pairs, seeds: int32/uint32 device tensors [n, 2]; x: int32 [n] or None.
     Returns dict(score int32 [n], beg int32 [n,2], end int32 [n,2],
@@ -162,6 +165,8 @@ def align_batch(store: ReadStore, pairs, seeds, x=None, x_scalar=0, k=17, match=
             _p(out["status"]), _p(out.get("cells")))
     if persistent:
         _lib.check(lib.xd_align_batch_persistent(*args, _tuning(tuning), _stream_ptr(stream)))
+    elif noalloc:
+        _lib.check(lib.xd_align_batch_noalloc(*args, _stream_ptr(stream)))
     else:
         _lib.check(lib.xd_align_batch(*args, _stream_ptr(stream)))
     return out

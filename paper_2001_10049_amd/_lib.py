@@ -22,7 +22,8 @@ OVERLAP_M_MAX = 64
 # every symbol include/xdrop.h declares
 EXPORTS = (
     "xd_pack_reads", "xd_store_create", "xd_store_create_from_codes", "xd_store_destroy",
-    "xd_store_info", "xd_align_batch", "xd_batch_scratch_bytes", "xd_align_batch_persistent",
+    "xd_store_info", "xd_align_batch", "xd_align_batch_noalloc", "xd_batch_scratch_bytes",
+    "xd_align_batch_persistent",
     "xd_align_pairs",
     "xd_banded_batch", "xd_banded_traceback", "xd_find_overlaps",
     "xd_plan_create",
@@ -116,6 +117,8 @@ def load() -> ctypes.CDLL:
     lib.xd_align_batch.argtypes = [vp, vp, vp, vp, i32, u64, i32, i32, i32, i32, vp, vp, vp,
                                    vp, vp, vp]
     lib.xd_align_batch.restype = ctypes.c_int
+    lib.xd_align_batch_noalloc.argtypes = lib.xd_align_batch.argtypes
+    lib.xd_align_batch_noalloc.restype = ctypes.c_int
     batch = [vp, vp, vp, vp, i32, u64, i32, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.xd_align_batch_persistent.argtypes = batch + [ctypes.POINTER(Tuning), vp]
     lib.xd_align_batch_persistent.restype = ctypes.c_int

@@ -1016,6 +1016,33 @@ struct xd_store {
   std::vector<uint32_t> host_len;
 };
 
+// Fixed device scratch for xd_align_batch_noalloc: one copy per device,
+// held until the process ends.  Host code never uses this name as an address
+// (it is a host-side stand-in): each device's copy is found with
+// hipGetSymbolAddress, once per device, and only that address is used.
+static __device__ __align__(256) char scratch[XD_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_noalloc_mu;
+static char* g_noalloc_ptr[64] = {};
+
+// the current device's copy of scratch (looked up on the first call there)
+static int noalloc_scratch(char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(XD_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(XD_EDEVICE, "hipGetSymbolAddress(scratch) returned null");
+    g_noalloc_ptr[dev] = (char*)p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return XD_OK;
+}
+
 struct xd_plan {
   BatchArgs args;
   Scratch scratch;
@@ -1325,6 +1352,32 @@ int xd_align_batch(const xd_store* store, const uint32_t* pairs, const uint32_t*
   Tuned tu;
   check_tuning(nullptr, tu);
   return batch_async(A, store->max_len, false, tu, (hipStream_t)hip_stream);
+}
+
+int xd_align_batch_noalloc(const xd_store* store, const uint32_t* pairs, const uint32_t* seeds,
+                           const int32_t* x, int32_t x_scalar, uint64_t n, int32_t k,
+                           int32_t match, int32_t mismatch, int32_t gap, int32_t* score,
+                           uint32_t* beg, uint32_t* end, int32_t* status, uint64_t* cells,
+                           void* hip_stream) {
+  BatchArgs A;
+  int rc = make_args(store, pairs, seeds, x, x_scalar, n, k, match, mismatch, gap, score, beg,
+                     end, status, cells, A);
+  if (rc) return rc;
+  if (n == 0) return XD_OK;
+  Tuned tu;
+  check_tuning(nullptr, tu);
+  const BandGeom g = band_geom(store->max_len, 1);
+  const uint64_t need = scratch_bytes(n, g);
+  if (need > XD_NOALLOC_SCRATCH_BYTES)
+    return fail(XD_EINVAL,
+                "xd_align_batch_noalloc: %llu tasks on reads of up to %u bases need %llu "
+                "scratch bytes; the fixed area holds %llu",
+                (unsigned long long)n, store->max_len, (unsigned long long)need,
+                (unsigned long long)XD_NOALLOC_SCRATCH_BYTES);
+  char* mem = nullptr;
+  rc = noalloc_scratch(&mem);
+  if (rc) return rc;
+  return enqueue(A, scratch_carve(mem, n, g), false, tu, (hipStream_t)hip_stream, false);
 }
 
 int xd_align_batch_persistent(const xd_store* store, const uint32_t* pairs,
