@@ -5,7 +5,10 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libxdrop.so")
+# XDROP_LIB=stamps selects the instrumented build of the same sources
+# (per-wave busy intervals, paper_2001_10049_amd/imbalance.py)
+_VARIANT = os.environ.get("XDROP_LIB", "")
+LIB_PATH = os.path.join(HERE, "libxdrop%s.so" % ("_" + _VARIANT if _VARIANT else ""))
 
 XD_OK, XD_EINVAL, XD_ENOMEM, XD_EDEVICE, XD_EAGAIN = 0, -1, -2, -3, -4
 TASK_OK, TASK_BAD_READ, TASK_BAD_SEED, TASK_BAD_X, TASK_BAND_OVERFLOW = 0, 1, 2, 3, 4
@@ -92,8 +95,8 @@ def load() -> ctypes.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libxdrop.so is not built (run __graft_entry__.build() or "
-                          "python -m paper_2001_10049_amd.build)")
+        raise ImportError("%s is not built (run __graft_entry__.build() or "
+                          "python -m paper_2001_10049_amd.build)" % os.path.basename(LIB_PATH))
     try:
         # torch's HIP runtime is loaded first so that the library binds to the
         # same instance; a process whose first HIP runtime came in with the

@@ -37,8 +37,48 @@
 #include "scan.h"
 #include "store_view.h"
 #include "xdrop_device.h"
+#include "pair_device.h"
 
 using xd::ExtOut;
+
+// Per-wave busy intervals of the extension kernels, compiled in only with
+// -DXD_WAVE_STAMPS (the instrumented build libxdrop_stamps.so).  Each wave
+// of k_ext_first, k_ext_tier, k_pair_tier and k_ext_band appends one record
+// of three words: start and end of the wave on the steady 100 MHz counter,
+// then kernel tag (bits 56..63), XCC_ID (48..51), HW_ID bits 0..15 (wave,
+// SIMD, CU, shader array and engine: 32..47) and work items taken (0..31).
+// Records past the armed capacity are counted but dropped.
+#ifdef XD_WAVE_STAMPS
+namespace stamps {
+__device__ unsigned long long* g_buf;
+__device__ uint32_t g_cap;
+__device__ uint32_t g_n;
+// kernel tags (k_ext_tier<CPL, ...> records kTier + CPL)
+enum : uint32_t { kFirst = 1, kPair = 0x20, kTier = 0x40, kBand = 0x80 };
+__device__ __forceinline__ uint64_t now() { return (uint64_t)wall_clock64(); }
+__device__ __forceinline__ void record(uint32_t tag, uint64_t t0, uint32_t items) {
+  if ((threadIdx.x & 63) != 0) return;
+  const uint64_t t1 = now();
+  const uint32_t hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);        // HW_ID
+  const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u;  // XCC_ID
+  const uint32_t i = atomicAdd(&g_n, 1u);
+  if (i >= g_cap) return;
+  g_buf[3ull * i] = t0;
+  g_buf[3ull * i + 1] = t1;
+  g_buf[3ull * i + 2] = ((uint64_t)tag << 56) | ((uint64_t)xcc << 48) |
+                        ((uint64_t)(hw & 0xffffu) << 32) | items;
+}
+}  // namespace stamps
+#define XD_STAMP_T0() const uint64_t xd_stamp_t0 = stamps::now()
+#define XD_STAMP(tag, items) stamps::record((tag), xd_stamp_t0, (items))
+#else
+#define XD_STAMP_T0() \
+  do {                \
+  } while (0)
+#define XD_STAMP(tag, items) \
+  do {                       \
+  } while (0)
+#endif
 
 namespace {
 
@@ -156,13 +196,14 @@ struct TierArgs {
   uint32_t* out_count;
 };
 
-static_assert(6 * sizeof(TierArgs) <= kTierArgsBytes, "tier argument area");
 static_assert(xd::kBandedMaxW == XD_BAND_MAX, "band limit");
 static_assert(sizeof(TierArgs) % 4 == 0, "tier arguments copied by words");
 
 struct TierPack {
   TierArgs t[6];
+  xd::pair::Shared pz;  // scalars of the packed 64-cell tier
 };
+static_assert(sizeof(TierPack) <= kTierArgsBytes, "tier argument area");
 
 // ---- per-task validation (shared by the extension and combine kernels) ----
 __device__ __forceinline__ int32_t task_status(const BatchArgs& A, uint32_t t, uint32_t& ra,
@@ -274,8 +315,10 @@ template <int CPL, int GS, bool UNIT>
 __global__ __launch_bounds__(64) void k_ext_first(BatchArgs A, uint32_t e0, uint32_t* ovf_list,
                                                   uint32_t* ovf_count) {
   __shared__ uint32_t ring[xd::Tier<CPL, GS>::LDS_WORDS];
+  XD_STAMP_T0();
   const uint32_t e = e0 + blockIdx.x;
   if (!run_ext<CPL, GS, UNIT>(A, e, ring)) push_list(ovf_list, ovf_count, e);
+  XD_STAMP(stamps::kFirst, 1u);
 }
 
 // Persistent waves (WAVES per block, each with its own ring).  Work item idx
@@ -290,6 +333,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_ext_tier(const TierArgs* __restr
   __shared__ uint32_t rings[WAVES][xd::Tier<CPL, GS>::LDS_WORDS];
   const int w = threadIdx.x >> 6;
   const TierArgs* pp = P;
+  XD_STAMP_T0();
+#ifdef XD_WAVE_STAMPS
+  uint32_t taken = 0;
+#endif
   for (;;) {
     // the arguments are re-read (scalar loads) after every extension instead
     // of being held in scalar registers through the extension's loop
@@ -305,6 +352,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_ext_tier(const TierArgs* __restr
     if (idx >= seg_len + n_in) break;
     const uint32_t e = __builtin_amdgcn_readfirstlane(
         idx < seg_len ? Q.queue[seg_lo + idx] : Q.in_list[idx - seg_len]);
+#ifdef XD_WAVE_STAMPS
+    ++taken;
+#endif
     if (!run_ext<CPL, GS, UNIT>(Q.A, e, rings[w])) {
       const TierArgs& R = *pp;
       if (R.out_list) {
@@ -315,6 +365,80 @@ __global__ __launch_bounds__(64 * WAVES) void k_ext_tier(const TierArgs* __restr
       }
     }
   }
+  XD_STAMP(stamps::kTier + CPL, taken);
+}
+
+// The batched form's 64-cell tier for match = 1 with two extensions per wave
+// (packed halves, xd::pair).  Work as for k_ext_tier: its queue segment, then
+// the previous tier's overflow list.  Extensions with X above the packed
+// limit go straight to the next tier's list.
+struct PairWork {
+  static constexpr bool kTrace = false;
+  const TierArgs* pp;
+  uint32_t seg_lo, seg_len, n_in;
+  uint32_t taken = 0;  // extensions started (instrumented build)
+  template <class... T>
+  __device__ void trace(T&&...) {}
+
+  __device__ void overflow(uint32_t e) {
+    const TierArgs& R = *pp;
+    if (R.out_list) {
+      push_list(R.out_list, R.out_count, e);
+    } else if (xd::lane_id() == 0) {
+      ExtOut o = {0, 0, 0, xd::kExtOverflow, 0};
+      R.A.ext[e] = o;
+    }
+  }
+  __device__ void done(uint32_t e, const ExtOut& o) {
+    if (xd::lane_id() == 0) pp->A.ext[e] = o;
+  }
+  __device__ bool next(uint32_t& e, xd::Ext& ex) {
+    for (;;) {
+      const TierArgs& Q = *pp;
+      uint32_t idx = 0;
+      if (xd::lane_id() == 0) idx = atomicAdd(Q.head, 1u);
+      idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
+      if (idx >= seg_len + n_in) return false;
+      e = __builtin_amdgcn_readfirstlane(idx < seg_len ? Q.queue[seg_lo + idx]
+                                                       : Q.in_list[idx - seg_len]);
+      if (!make_ext(Q.A, e, ex)) {
+        if (xd::lane_id() == 0) {
+          ExtOut o = {0, 0, 0, xd::kExtInvalid, 0};
+          Q.A.ext[e] = o;
+        }
+        continue;
+      }
+      if (ex.X > xd::pair::kXMax) {
+        overflow(e);
+        continue;
+      }
+#ifdef XD_WAVE_STAMPS
+      ++taken;
+#endif
+      return true;
+    }
+  }
+};
+
+// (at most 80 VGPRs, so 6 waves share a SIMD; the natural allocation of 85
+// leaves room for 5)
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
+void k_pair_tier(const TierArgs* __restrict__ P,
+                                                          const xd::pair::Shared* Zp) {
+  static_assert(WAVES * xd::pair::WAVE_WORDS * 4 <= 64 * 1024, "LDS per block");
+  __shared__ uint32_t lds[WAVES][xd::pair::WAVE_WORDS];
+  const int w = threadIdx.x >> 6;
+  const TierArgs& Q = *P;
+  PairWork W;
+  W.pp = P;
+  W.seg_lo = Q.seg ? __builtin_amdgcn_readfirstlane(Q.seg[0]) : 0u;
+  W.seg_len = Q.seg ? __builtin_amdgcn_readfirstlane(Q.seg[1]) - W.seg_lo : 0u;
+  W.n_in = Q.in_count ? __builtin_amdgcn_readfirstlane(*Q.in_count) : 0u;
+  if (W.seg_len + W.n_in == 0) return;  // no work: leave without touching the shared head
+  XD_STAMP_T0();
+  xd::pair::run(W, lds[w], Zp);
+  XD_STAMP(stamps::kPair, W.taken);
 }
 
 // Band tier: persistent workgroups of kBandWaves waves, each taking the next
@@ -328,6 +452,8 @@ __global__ __launch_bounds__(64 * kBandWaves) void k_ext_band(const TierArgs* __
   __shared__ uint32_t item;
   int32_t* buf = band + (uint64_t)blockIdx.x * 3ull * (uint64_t)cap;
   const TierArgs& Q = *P;
+  XD_STAMP_T0();
+  uint32_t taken = 0;
   for (;;) {
     if (threadIdx.x == 0) {
       const uint32_t n_in = *Q.in_count;
@@ -338,11 +464,14 @@ __global__ __launch_bounds__(64 * kBandWaves) void k_ext_band(const TierArgs* __
     const uint32_t e = item;
     __syncthreads();  // item is read before thread 0 takes the next one
     if (e == 0xffffffffu) break;
+    ++taken;
     xd::Ext ex;
     ExtOut o = {0, 0, 0, xd::kExtInvalid, 0};
     if (make_ext(Q.A, e, ex)) xd::extend_band<kBandWaves>(ex, Q.A.sc, buf, cap, part, csum, o);
     if (threadIdx.x == 0) Q.A.ext[e] = o;
   }
+  if (threadIdx.x < 64) XD_STAMP(stamps::kBand, taken);
+  (void)taken;
 }
 
 // ---- queue: tier-major, longest first ------------------------------------
@@ -843,6 +972,26 @@ int device_cus() {
   return cus;
 }
 
+// The packed two-extension tier handles match = 1 when the diagonal bonus
+// mismatch + 2g (+ 1 - mismatch on a match) fits a byte and g leaves room
+// for a group between rebases (see pair_device.h).
+bool pair_ok(const xd::Scoring& sc) {
+  const int32_t g = -sc.G;
+  return sc.M == 1 && sc.MM + 2 * g >= 0 && g <= xd::pair::kGapMax;
+}
+
+xd::pair::Shared pair_shared(const xd::Scoring& sc) {
+  const int32_t g = -sc.G;
+  const uint32_t C = (uint32_t)(sc.MM + 2 * g);
+  xd::pair::Shared z;
+  z.g = g;
+  z.ringw = C * 0x01010101u;
+  z.dM = (uint32_t)(sc.M - sc.MM);
+  z.G1 = (uint32_t)g * 0x10001u;
+  z.GB1 = z.G1 + 0x10000u;
+  return z;
+}
+
 // tier arguments: tier 0 (64 cells, batched form), tiers 1..4 (128, 256, 512,
 // 1024 cells) and the band tier, each with its queue segment (batched form;
 // segments 0..2 hold the extensions whose X picks that first tier) and the
@@ -861,6 +1010,7 @@ TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
   p.t[4] = {A, S.queue, nullptr, S.ovf[3], c + kOvfCount + 3, c + kHead + 4, S.ovf[4],
             c + kOvfCount + 4};
   p.t[5] = {A, S.queue, nullptr, S.ovf[4], c + kOvfCount + 4, c + kBandHead, nullptr, nullptr};
+  p.pz = pair_shared(A.sc);
   return p;
 }
 
@@ -875,6 +1025,14 @@ void launch_wide(const Scratch& S, uint32_t blocks, hipStream_t stream) {
                      ta + 4);
   hipLaunchKernelGGL(k_ext_band, dim3(S.geom.blocks), dim3(64 * kBandWaves), 0, stream, ta + 5,
                      S.band, S.geom.cap);
+}
+
+constexpr int kPairWaves = 4;  // waves per block of the packed tier
+
+void launch_pair(const Scratch& S, uint32_t blocks, hipStream_t stream) {
+  const TierPack* tp = (const TierPack*)S.targs;
+  hipLaunchKernelGGL((k_pair_tier<kPairWaves>), dim3(blocks), dim3(64 * kPairWaves), 0, stream,
+                     &tp->t[0], &tp->pz);
 }
 
 template <bool UNIT>
@@ -910,7 +1068,9 @@ void launch_persistent_ext(const BatchArgs& A, const Scratch& S, uint64_t n_ext,
                      dim3(256), 0, stream, A, R, (uint32_t)n_ext, S.hist, S.queue);
   uint32_t blocks = (uint32_t)device_cus() * (uint32_t)tu.waves_per_cu / 4u;
   if (blocks < 1) blocks = 1;
-  if (tu.group_steps == 4)
+  if (UNIT && pair_ok(A.sc))
+    launch_pair(S, blocks, stream);
+  else if (tu.group_steps == 4)
     launch_tier0<UNIT, 4>(S, blocks, stream);
   else if (tu.group_steps == 16)
     launch_tier0<UNIT, 16>(S, blocks, stream);
@@ -1673,6 +1833,38 @@ void xd_plan_destroy(xd_plan* p) {
   if (p->mem) (void)hipFree(p->mem);
   delete p;
 }
+
+#ifdef XD_WAVE_STAMPS
+// instrumented build only: arm the per-wave records (buf: device memory for
+// cap records of three 64-bit words; null disarms) and read how many waves
+// recorded since the last arm (including the dropped ones past cap)
+int xd_debug_stamps_arm(void* buf, uint32_t cap) {
+  HIP_TRY(hipDeviceSynchronize());
+  unsigned long long* b = (unsigned long long*)buf;
+  const uint32_t c = buf ? cap : 0u, z = 0;
+  HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(stamps::g_buf), &b, sizeof(b)));
+  HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(stamps::g_cap), &c, sizeof(c)));
+  HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(stamps::g_n), &z, sizeof(z)));
+  return XD_OK;
+}
+
+int xd_debug_stamps_count(uint32_t* n) {
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpyFromSymbol(n, HIP_SYMBOL(stamps::g_n), sizeof(*n)));
+  return XD_OK;
+}
+#endif
+
+#ifdef XD_PAIR_EVENTS
+// counting build only: the pair runner's event counts (read and cleared)
+int xd_debug_pair_events(unsigned long long* out) {
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpyFromSymbol(out, HIP_SYMBOL(xd::pair::g_pair_events), 16 * 8));
+  unsigned long long z[16] = {};
+  HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(xd::pair::g_pair_events), z, 16 * 8));
+  return XD_OK;
+}
+#endif
 
 int xd_profile_enable(int on) {
   g_prof_on.store(on ? 1 : 0);
