@@ -69,7 +69,14 @@ extern "C" {
 
 /* limits (checked; violations return XD_EINVAL) */
 #define XD_X_MAX (1 << 20)           /* largest X */
-#define XD_SCORE_LIMIT 127           /* 1 <= match <= 127, -127 <= mismatch < match, -127 <= gap <= -1 */
+/* X-drop scoring (xd_align_*, xd_plan_*, xd_server_*): 1 <= match <= 1000,
+ * -1000 <= mismatch < match, -1000 <= gap <= -1, and match times the store's
+ * longest read at most 2^31 - 1, so that every score is an int32 (paper
+ * section 2 scores alignments with a match score and mismatch and gap
+ * penalties; their range is this library's choice). */
+#define XD_SCORE_LIMIT 1000
+/* banded Smith-Waterman scoring (xd_banded_*): the same rules with 127 */
+#define XD_BANDED_SCORE_LIMIT 127
 #define XD_READ_MAX (1u << 22)       /* longest read, bases */
 
 typedef struct xd_store xd_store;

@@ -17,7 +17,8 @@ TASK_OPS_OVERFLOW, TASK_TRACE_FAULT = 6, 7
 OP_M, OP_I, OP_D = 0, 1, 2
 X_MAX = 1 << 20
 BAND_MAX = 48
-SCORE_LIMIT = 127
+SCORE_LIMIT = 1000
+BANDED_SCORE_LIMIT = 127
 READ_MAX = 1 << 22
 OVERLAP_K_MAX = 31
 OVERLAP_M_MAX = 64

@@ -296,6 +296,10 @@ int xd_server_create(const xd_store* store, const xd_server_config* cfg, xd_serv
   const int sc = xd_internal_check_scoring(cfg->k, cfg->match, cfg->mismatch, cfg->gap);
   if (sc) return sc;
   if (!store) return set_err(XD_EINVAL, "xd_server_create: null store");
+  uint32_t longest = 0;
+  if (xd_store_info(store, nullptr, nullptr, &longest) == XD_OK &&
+      (uint64_t)cfg->match * longest > (uint64_t)INT32_MAX)
+    return set_err(XD_EINVAL, "xd_server_create: match times the longest read exceeds 2^31 - 1");
   xd_server* S = new xd_server();
   S->store = store;
   S->cfg = *cfg;

@@ -1106,17 +1106,30 @@ int hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, #call);  \
   } while (0)
 
-int check_scoring(int32_t k, int32_t match, int32_t mismatch, int32_t gap) {
+// limit: XD_SCORE_LIMIT for the X-drop calls, XD_BANDED_SCORE_LIMIT for the
+// banded ones
+int check_scoring(int32_t k, int32_t match, int32_t mismatch, int32_t gap,
+                  int32_t limit = XD_SCORE_LIMIT) {
   if (k < 1) return fail(XD_EINVAL, "k must be >= 1 (got %d)", k);
-  if (match < 1 || match > XD_SCORE_LIMIT)
-    return fail(XD_EINVAL, "match must be in [1, %d] (got %d)", XD_SCORE_LIMIT, match);
-  if (mismatch >= match || mismatch < -XD_SCORE_LIMIT)
-    return fail(XD_EINVAL, "mismatch must be in [-%d, match) (got %d)", XD_SCORE_LIMIT,
-                mismatch);
-  if (gap > -1 || gap < -XD_SCORE_LIMIT)
-    return fail(XD_EINVAL, "gap must be in [-%d, -1] (got %d)", XD_SCORE_LIMIT, gap);
+  if (match < 1 || match > limit)
+    return fail(XD_EINVAL, "match must be in [1, %d] (got %d)", limit, match);
+  if (mismatch >= match || mismatch < -limit)
+    return fail(XD_EINVAL, "mismatch must be in [-%d, match) (got %d)", limit, mismatch);
+  if (gap > -1 || gap < -limit)
+    return fail(XD_EINVAL, "gap must be in [-%d, -1] (got %d)", limit, gap);
   return XD_OK;
 }
+
+// every score is at most match * (shorter read's length): keep it an int32
+int check_score_range(uint32_t max_len, int32_t match) {
+  if ((uint64_t)match * max_len > (uint64_t)INT32_MAX)
+    return fail(XD_EINVAL, "match %d times the store's longest read (%u) exceeds 2^31 - 1",
+                match, max_len);
+  return XD_OK;
+}
+
+// the 64-cell tiers' UNIT form: match = 1 and a byte-sized match bonus
+bool unit_scoring(const xd::Scoring& sc) { return sc.M == 1 && sc.M - sc.MM <= 255; }
 
 int check_tuning(const xd_tuning* t, Tuned& out) {
   out.waves_per_cu = 32;
@@ -1228,6 +1241,8 @@ int make_args(const xd_store* store, const uint32_t* pairs, const uint32_t* seed
   if (n > (1ull << 30)) return fail(XD_EINVAL, "n = %llu exceeds 2^30", (unsigned long long)n);
   if (n && (!pairs || !seeds || !score || !beg || !end || !status))
     return fail(XD_EINVAL, "null task or result array");
+  rc = check_score_range(store->max_len, match);
+  if (rc) return rc;
   A.st = {store->words, store->word_off, store->len, store->n_reads};
   A.pairs = pairs;
   A.seeds = seeds;
@@ -1263,13 +1278,13 @@ int enqueue(BatchArgs A, const Scratch& S, bool persistent, const Tuned& tu,
                      make_pack(A, S, persistent), (uint32_t*)S.targs);
   if (persistent) {
     if (prof) HIP_TRY(hipEventRecord(rec.ev[0], stream));
-    if (A.sc.M == 1)
+    if (unit_scoring(A.sc))
       launch_persistent_ext<true>(A, S, n_ext, tu, prof ? rec.ev : nullptr, stream);
     else
       launch_persistent_ext<false>(A, S, n_ext, tu, prof ? rec.ev : nullptr, stream);
   } else {
     if (prof) HIP_TRY(hipEventRecord(rec.ev[0], stream));
-    if (A.sc.M == 1)
+    if (unit_scoring(A.sc))
       launch_plain_ext<true>(A, S, n_ext, prof ? rec.ev : nullptr, stream);
     else
       launch_plain_ext<false>(A, S, n_ext, prof ? rec.ev : nullptr, stream);
@@ -1581,6 +1596,8 @@ int xd_align_pairs(const xd_store* store, uint64_t n_pairs, const uint32_t* pair
   rc_ = check_tuning(tuning, tu);
   if (rc_) return rc_;
   if (n_pairs == 0) return XD_OK;
+  rc_ = check_score_range(store->max_len, match);
+  if (rc_) return rc_;
   hipStream_t stream = (hipStream_t)hip_stream;
   const BandGeom g = band_geom(store->max_len, (uint32_t)tu.band_blocks);
   const uint64_t S = n_seeds;
@@ -1653,7 +1670,7 @@ int xd_banded_batch(const xd_store* store, const uint32_t* pairs, const uint32_t
                     int32_t mismatch, int32_t gap, int32_t* score, uint32_t* end,
                     int32_t* status, uint64_t* cells, void* hip_stream) {
   if (!store) return fail(XD_EINVAL, "xd_banded_batch: store is null");
-  int rc = check_scoring(k, match, mismatch, gap);
+  int rc = check_scoring(k, match, mismatch, gap, XD_BANDED_SCORE_LIMIT);
   if (rc) return rc;
   if (!w && (w_scalar < 0 || w_scalar > XD_BAND_MAX))
     return fail(XD_EINVAL, "w_scalar must be in [0, %d] (got %d)", XD_BAND_MAX, w_scalar);
@@ -1700,7 +1717,7 @@ int xd_banded_traceback(const xd_store* store, const uint32_t* pairs, const uint
                         int32_t* score, uint32_t* beg, uint32_t* end, int32_t* status,
                         uint64_t* cells, uint32_t* ops, uint32_t* n_ops, void* hip_stream) {
   if (!store) return fail(XD_EINVAL, "xd_banded_traceback: store is null");
-  int rc = check_scoring(k, match, mismatch, gap);
+  int rc = check_scoring(k, match, mismatch, gap, XD_BANDED_SCORE_LIMIT);
   if (rc) return rc;
   if (!w && (w_scalar < 0 || w_scalar > XD_BAND_MAX))
     return fail(XD_EINVAL, "w_scalar must be in [0, %d] (got %d)", XD_BAND_MAX, w_scalar);

@@ -26,9 +26,12 @@
 // caller re-runs it in a wider tier, so no result is ever truncated.
 //
 // b is read through a per-wave LDS ring of encoded bases:
-//   ring[j mod RING] = (match - mismatch) << (8 * code(b_j))
+//   ring[j mod RING] = (match - mismatch) << (8 * code(b_j))   (UNIT)
+//   ring[j mod RING] = 1 << (8 * code(b_j))                    (otherwise)
 // read one byte at a time at byte offset code(a_i) within the word, so one
-// ds_read_u8 gives a cell's match bonus.  The codes of a sit in a second
+// ds_read_u8 gives a cell's match bonus (UNIT, where match - mismatch fits a
+// byte) or its match indicator, which one multiply turns into the bonus for
+// any match - mismatch up to 2000.  The codes of a sit in a second
 // ring (one byte per row).  Both rings are refilled 64 positions at a time
 // from the packed read store; the next chunk is always already on its way
 // in a register (loaded one refill ahead), so refills do not wait for HBM.
@@ -43,6 +46,13 @@ namespace xd {
 
 constexpr int32_t kEvMin = 4096;  // evaluated cells have s > kEvMin
 constexpr int32_t kBias0 = 8192;  // bias = X + kBias0 keeps live U >= 8192
+// U grows by up to match/2 + g per antidiagonal.  Once the threshold passes
+// kRebaseAt, every live U and the threshold drop by the same amount so that
+// the threshold is kRebaseTo again (dead cells stay 0); the amount is added
+// back to the score at the end.  Between two checks (one group, at most 16
+// antidiagonals) U rises by at most 16 * 1500 + X < 2^30.
+constexpr int32_t kRebaseAt = 1 << 30;
+constexpr int32_t kRebaseTo = 1 << 20;
 
 struct ExtOut {
   int32_t best;
@@ -270,8 +280,8 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
   auto fill_to = [&](int32_t jhi) {
     while (filled < jhi) {
       const int32_t j = filled + 1 + lane;
-      const uint32_t v =
-          (j >= 1 & j <= n) ? (dM << (8u * (code_in(pf_b, e.ob, e.dirb, j) ^ e.comp))) : 0u;
+      const uint32_t sh = 8u * (code_in(pf_b, e.ob, e.dirb, j) ^ e.comp);
+      const uint32_t v = (j >= 1 & j <= n) ? ((UNIT ? dM : 1u) << sh) : 0u;
       const int slot = j & MASK;
       ring[slot] = v;
       if (slot < MIR) ring[RING + slot] = v;
@@ -299,6 +309,15 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
     for (int c = 0; c < CPL; ++c) aa[c] = aring[(base + lane * CPL + c) & (RA - 1)];
   };
   load_a();
+  if constexpr (!UNIT) {
+    // Window rows above the antidiagonal's end (j in [2 - Q, -1], outside
+    // the grid) read ring slots RING - Q .. RING - 1 before any fill reaches
+    // them.  Their cells derive only from each other and must stay below
+    // kEvMin; a match indicator left over in LDS, times the bonus, could
+    // lift them above it, so these slots start at 0.  (UNIT bonuses are
+    // bytes: any leftover keeps such a cell below kEvMin.)
+    for (int q = RING - Q + lane; q < RING; q += 64) ring[q] = 0u;
+  }
 
   // live masks per slot: Lc for the last antidiagonal d, Lp for d-1
   uint64_t Lc[CPL], Lp[CPL];
@@ -312,7 +331,12 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
   // threshold for antidiagonal d+1 in U units: T_d - X + g*(d+1) + bias;
   // the improvement threshold is thr + X
   int32_t thr = g + kBias0;
+  int64_t rebased = 0;  // total taken off U and thr (kRebaseAt)
   uint32_t cnt = 0;  // evaluated cells of this lane
+  // a cell's match bonus from its ring byte
+  auto bonus = [&](uint32_t b) -> int32_t {
+    return UNIT ? (int32_t)b : (int32_t)dM * (int32_t)b;
+  };
   int32_t irow = lane * CPL;  // row of this lane's slot 0 minus base
 
   // G antidiagonals d+1 .. d+G (G = GS, or 4 when the band is near the top
@@ -348,7 +372,7 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
       uint64_t any = 0;
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
-        int32_t s = max(max(Up[c] + (int32_t)bmv[t][c] + C, upv[c]), U1[c]);
+        int32_t s = max(max(Up[c] + bonus(bmv[t][c]) + C, upv[c]), U1[c]);
         if (MASKED) {
           const int32_t i = base + irow + c;
           const bool out = (i > m) | (i < dn - n);
@@ -451,7 +475,7 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
       uint64_t any = 0, L[CPL];
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
-        const int32_t sv = max(max(Up[c] + (int32_t)bmv[t][c] + C, upv[c]), U1[c]);
+        const int32_t sv = max(max(Up[c] + bonus(bmv[t][c]) + C, upv[c]), U1[c]);
         if constexpr (!by_masks) cnt += (sv > kEvMin) ? 1u : 0u;
         const bool lv = sv >= thr;
         L[c] = ballot64(lv);
@@ -499,7 +523,7 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
       const int32_t lo = sctz64(M);
       const int32_t dv = d - base;
       const int32_t c = (z - GS) | (z + (m - base - 63 - GS)) | (lo - dv + (n - GS)) |
-                        (filled - dv - GS);
+                        (filled - dv - GS) | (kRebaseAt - thr);
       if (c >= 0) {
         group_unit(std::integral_constant<int, GS>{});
         continue;
@@ -539,7 +563,7 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
       }
       const int32_t dv = d - base;
       const int32_t c = hi | (Q - 1 - GS - hi) | (m - base - hi - GS) | (lo - dv + (n - GS)) |
-                        (filled - dv - GS);
+                        (filled - dv - GS) | (kRebaseAt - thr);
       if (c >= 0) {
         group_unit(std::integral_constant<int, GS>{});
         continue;
@@ -567,6 +591,17 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
           continue;
         }
       }
+    }
+    if (thr > kRebaseAt) {
+      const int32_t R = thr - kRebaseTo;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        U1[c] = U1[c] ? U1[c] - R : 0;
+        Up[c] = Up[c] ? Up[c] - R : 0;
+      }
+      thr -= R;
+      rebased += R;
+      continue;
     }
     int32_t lo = Q, hi = -1;
 #pragma unroll
@@ -633,8 +668,8 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
   }
   if (overflow) return false;
   const uint64_t cells = wave_sum_u64(cnt);
-  // thr = T - X + g*(d+1) + bias after the last antidiagonal d
-  res.best = thr + X - g * (d + 1) - bias;
+  // thr + rebased = T - X + g*(d+1) + bias after the last antidiagonal d
+  res.best = (int32_t)((int64_t)thr + rebased + X - (int64_t)g * (d + 1) - bias);
   res.bi = bi;
   res.bj = dstar - bi;
   res.flags = kExtDone;
@@ -688,7 +723,8 @@ __device__ __forceinline__ void extend_band(const Ext& e, const Scoring& sc,
   int32_t wlo2 = 0, whi2 = -1, llo2 = 0, lhi2 = -1;
   if (tid == 0) r1[0] = bias;  // antidiagonal 0: the origin, U(0,0) = bias
   __syncthreads();
-  int32_t thr = g + kBias0;  // T_d - X + g*(d+1) + bias
+  int32_t thr = g + kBias0;  // T_d - X + g*(d+1) + bias - rebased
+  int64_t rebased = 0;
   int32_t bi = 0, dstar = 0;
   uint64_t cnt = 0;
   int32_t d = 0;
@@ -696,6 +732,14 @@ __device__ __forceinline__ void extend_band(const Ext& e, const Scoring& sc,
   for (;;) {
     const bool live1 = llo1 <= lhi1, live2 = llo2 <= lhi2;
     if ((!live1 && !live2) || d >= m + n) break;
+    if (thr > kRebaseAt) {  // as in extend: every stored U and thr drop by R
+      const int32_t R = thr - kRebaseTo;
+      for (int32_t i = wlo1 + tid; i <= whi1; i += 64 * NW) r1[i] = r1[i] ? r1[i] - R : 0;
+      for (int32_t i = wlo2 + tid; i <= whi2; i += 64 * NW) r2[i] = r2[i] ? r2[i] - R : 0;
+      thr -= R;
+      rebased += R;
+      __syncthreads();
+    }
     const int32_t dn = d + 1;
     // rows of dn with a predecessor in a live range: left/up from d,
     // diagonal from d-1, inside the grid
@@ -788,7 +832,7 @@ __device__ __forceinline__ void extend_band(const Ext& e, const Scoring& sc,
 #pragma unroll
   for (int q = 0; q < NW; ++q) cells += csum[q];
   __syncthreads();  // csum and part are free for the next extension
-  res.best = thr + X - g * (d + 1) - bias;
+  res.best = (int32_t)((int64_t)thr + rebased + X - (int64_t)g * (d + 1) - bias);
   res.bi = bi;
   res.bj = dstar - bi;
   res.flags = kExtDone;

@@ -70,7 +70,8 @@ def test_align_batch_argument_errors_without_device():
 
 
 @pytest.mark.parametrize("k,m,mm,g", [(0, 1, -1, -1), (17, 0, -1, -1), (17, 1, 1, -1),
-                                      (17, 1, -1, 0), (17, 200, -1, -1), (17, 1, -1, -200)])
+                                      (17, 1, -1, 0), (17, 1001, -1, -1), (17, 1, -1, -1001),
+                                      (17, 1, -1001, -1), (17, 5, 5, -1)])
 def test_align_batch_rejects_bad_scoring(k, m, mm, g):
     lib = _lib.load()
     dummy = ctypes.c_void_p(1)  # never dereferenced: scalar checks come first
@@ -126,6 +127,10 @@ def test_banded_traceback_argument_errors_without_device():
     assert b"store" in lib.xd_last_error()
     assert call(dummy, k=0) == _lib.XD_EINVAL
     assert call(dummy, mm=2) == _lib.XD_EINVAL
+    # banded scoring stays within +-127
+    assert call(dummy, m=128) == _lib.XD_EINVAL and b"127" in lib.xd_last_error()
+    assert call(dummy, g=-128) == _lib.XD_EINVAL
+    assert call(dummy, mm=-128) == _lib.XD_EINVAL
     assert call(dummy, w_scalar=_lib.BAND_MAX + 1) == _lib.XD_EINVAL
     assert call(dummy, w_scalar=-1) == _lib.XD_EINVAL
     assert call(dummy, n=1) == _lib.XD_EINVAL          # null task and result arrays
@@ -165,7 +170,8 @@ def test_server_request_bytes_cover_the_batch():
 def test_server_create_rejects_bad_scoring():
     lib = _lib.load()
     h = ctypes.c_void_p()
-    for k, m, mm, g in [(0, 1, -1, -1), (17, 0, -1, -1), (17, 1, 1, -1), (17, 1, -1, 0)]:
+    for k, m, mm, g in [(0, 1, -1, -1), (17, 0, -1, -1), (17, 1, 1, -1), (17, 1, -1, 0),
+                        (17, 1001, -1, -1), (17, 1, -1, -1001)]:
         cfg = _lib.ServerConfig(1 << 30, 1, 0, 0, k, m, mm, g, _lib.Tuning())
         # the dummy store is never dereferenced: the scheme is checked first
         rc = lib.xd_server_create(ctypes.c_void_p(1), ctypes.byref(cfg), ctypes.byref(h))
