@@ -11,7 +11,12 @@ before the timed region; the read store upload is not timed.
 
 Prints one JSON line: GCUPS (evaluated cells of both extensions per second,
 the oracle's cell definition) as `value`, pairs/s beside it, the dominant
-kernel's roofline position and the CPU oracle timed on a bounded sample.
+kernel's roofline position and the CPU oracle timed on a bounded sample
+(all host threads, then one; the host CPU model).  Beside them: the batched
+form's packed tier against the int32 and packed 16-bit peaks, the
+2,000,000-task c3 workload (X in {7, 25, 50}) plain against batched, and a
+short c5 serving window (Poisson requests, p50/p99 latency and pairs/s;
+bench_serve.py runs the full 20 s window).
 """
 from __future__ import annotations
 
@@ -30,7 +35,7 @@ METRIC = "GCUPS and aligned pairs/sec for X-drop extension at X=25 (1 MI355X)"
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
 OPS_PER_CELL = 8  # compare, select, add diagonal, max(up,left), add gap, max, compare, select
 KERNEL_NAMES = {"plain": "k_ext_first<1, 16, true>",
-                "persistent": "k_ext_tier<1, GS, true, 4> (64-cell tier, queue)"}
+                "persistent": "k_pair_tier<4> (64-cell tier, two extensions per wave, queue)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
 
 WORKLOAD_DESC = {
@@ -55,7 +60,7 @@ def kernel_source_hash() -> str:
     """Hash of the sources the extension kernels and their launches are built from."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2001_10049_amd", "csrc")
-    for f in ("xdrop.hip", "xdrop_device.h"):
+    for f in ("xdrop.hip", "xdrop_device.h", "pair_device.h"):
         h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -82,11 +87,23 @@ def xd_tuned(w):
         return {}
 
 
-def cpu_baseline(w, seconds: float):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, seconds: float, threads: int | None = None):
+    """The oracle as it stands, on the first tasks of w for about `seconds`."""
     import numpy as np
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    chunk = 2000
+    if threads is None:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    chunk = 2000 if threads > 1 else 200
     done = cells = 0
     t0 = time.perf_counter()
     while done < w.n_tasks and time.perf_counter() - t0 < seconds:
@@ -102,40 +119,11 @@ def cpu_baseline(w, seconds: float):
             "sample": "first %d tasks of %s (%.1f s wall, %d cells)" % (done, w.name, dt, cells)}
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_DESC))
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--forms", default="plain,persistent,plan",
-                    help="forms to time; the first one gives `value`")
-    ap.add_argument("--tuning", default="",
-                    help="JSON tuning for the batched forms (default: the tuned cache entry)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
-
+def time_forms(xd, torch, w, forms, steps, warmup, tuning, dev, label):
+    """Times each form on workload w (same output buffers, results checked
+    equal across forms); returns (per-form results, profile of the first
+    profiled form, cells per step)."""
     import numpy as np
-    import torch
-
-    import synth
-    import paper_2001_10049_amd as xd
-
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(2)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-
-    log("generating", args.workload)
-    w = synth.config(args.workload)
     store = xd.ReadStore.from_workload(w)
     pairs, seeds, x = xd.workload_tensors(w, dev)
     n = w.n_tasks
@@ -144,9 +132,6 @@ def main():
                end=torch.empty((n, 2), dtype=torch.int32, device=dev),
                status=torch.empty(n, dtype=torch.int32, device=dev),
                cells=torch.empty(n, dtype=torch.int64, device=dev))
-
-    tuning = json.loads(args.tuning) if args.tuning else xd_tuned(w)
-    forms = [f for f in args.forms.split(",") if f]
     plan = None
     if "plan" in forms:
         plan = xd.Plan(store, pairs, seeds, x=x, k=w.k, out=out, tuning=tuning)
@@ -156,27 +141,27 @@ def main():
                                              persistent=True, tuning=tuning),
         "plan": lambda: plan.launch(),
     }
-    results = {}
+    results, profs = {}, {}
     ref_out = None
-    prof = None
+    cells_per_step = 0
     for form in forms:
         step = steppers[form]
-        log("warmup", form, args.warmup)
-        for _ in range(args.warmup):
+        log(label, "warmup", form, warmup)
+        for _ in range(warmup):
             step()
         if form != "plan":
             xd.profile_enable(True)
             xd.profile_read(reset=True)
-        log("timing", form, args.steps, "steps")
+        log(label, "timing", form, steps, "steps")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         p = xd.profile_read(reset=True) if form != "plan" else None
         xd.profile_enable(False)
-        ms_f = (t1 - t0) * 1e3 / args.steps
+        ms_f = (t1 - t0) * 1e3 / steps
         # every step computes the same results: check and count them now
         if int((out["status"] != 0).sum()) != 0:
             raise RuntimeError("tasks failed: %s" % np.unique(out["status"].cpu().numpy()))
@@ -191,13 +176,63 @@ def main():
                          "pairs_per_s": round(n / (ms_f / 1e3), 1)}
         if p is not None:
             results[form]["ms_tier1_per_launch"] = round(p["ms_tier1"] / max(p["batches"], 1), 4)
-        if prof is None:
-            prof = p
+            profs[form] = p
     if plan is not None:
         plan.close()
+    store.close()
+    del out, pairs, seeds, x
+    torch.cuda.empty_cache()
+    return results, profs, cells_per_step
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_DESC))
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu1-seconds", type=float, default=6.0,
+                    help="one-thread oracle sample (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (for HBM counter scaling)")
+    ap.add_argument("--forms", default="plain,persistent,plan",
+                    help="forms to time; the first one gives `value`")
+    ap.add_argument("--tuning", default="",
+                    help="JSON tuning for the batched forms (default: the tuned cache entry)")
+    ap.add_argument("--c3-steps", type=int, default=3,
+                    help="steps of the c3 plain-vs-batched comparison (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="measured window of the c5 serving run (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    import paper_2001_10049_amd as xd
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    log("generating", args.workload)
+    w = synth.config(args.workload)
+    n = w.n_tasks
+    tuning = json.loads(args.tuning) if args.tuning else xd_tuned(w)
+    forms = [f for f in args.forms.split(",") if f]
+    results, profs, cells_per_step = time_forms(xd, torch, w, forms, args.steps, args.warmup,
+                                                tuning, dev, args.workload)
     head = forms[0]
     ms = results[head]["ms_per_step"]
     gcups = results[head]["gcups"]
+    prof = profs.get(head) or next(iter(profs.values()))
 
     # dominant kernel: the 64-cell first tier; its algorithmic work is every
     # cell it completes (all cells when no extension moved to a wider tier)
@@ -218,6 +253,21 @@ def main():
                 "ext_overflowed": [int(prof["to_tier2"]), int(prof["to_tier3"]),
                                    int(prof["to_tier4"]), int(prof["to_tier5"]),
                                    int(prof["to_band"])]}
+    # the batched form's packed tier (two extensions per wave, 16-bit halves)
+    # against both peaks: int32 lanes, and packed 16-bit lanes (twice that)
+    # (only when that tier runs every extension: no X above its limit, no
+    # overflow into the 128-cell tier)
+    pp = profs.get("persistent")
+    packed = None
+    if pp is not None and pp["to_tier2"] == 0 and int(w.x.max()) <= tuning.get("x_tier1", 32):
+        pk_ms = pp["ms_tier1"] / max(pp["batches"], 1)
+        pk_ach = OPS_PER_CELL * cells_per_step / (pk_ms / 1e3) / 1e12
+        packed = {"kernel": KERNEL_NAMES["persistent"], "ms_per_launch": round(pk_ms, 4),
+                  "kernel_gcups": round(cells_per_step / (pk_ms / 1e3) / 1e9, 2),
+                  "achieved": round(pk_ach, 3), "unit": "TOP/s",
+                  "frac_int32_peak": round(pk_ach / PEAK_INT32_TOPS, 4),
+                  "peak_packed16": round(2 * PEAK_INT32_TOPS, 3),
+                  "frac_packed16_peak": round(pk_ach / (2 * PEAK_INT32_TOPS), 4)}
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.int32, device=dev)  # 1 GiB
@@ -227,10 +277,35 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    # c3: batched (queue + persistent tiers, hipGraph plan) against plain on
+    # the uneven 2,000,000-task workload
+    c3 = None
+    if args.c3_steps > 0 and args.workload != "c3":
+        log("generating c3")
+        w3 = synth.config("c3")
+        r3, _, cells3 = time_forms(xd, torch, w3, ["plain", "persistent", "plan"],
+                                   args.c3_steps, 1, xd_tuned(w3), dev, "c3")
+        c3 = {"workload": WORKLOAD_DESC["c3"], "steps": args.c3_steps,
+              "cells_per_step": cells3, "forms": r3,
+              "batched_over_plain": round(r3["plan"]["gcups"] / r3["plain"]["gcups"], 3)}
+        del w3
+
+    serving = None
+    if args.serve_seconds > 0:
+        log("serving window (c5), %.0f s" % args.serve_seconds)
+        import bench_serve
+        serving = bench_serve.run(seconds=args.serve_seconds, warmup=1.0)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle), about %.0f s" % args.cpu_seconds)
         cpu = cpu_baseline(w, args.cpu_seconds)
+        cpu["cpu_model"] = cpu_model()
+        if args.cpu1_seconds > 0:
+            log("cpu baseline, one thread, about %.0f s" % args.cpu1_seconds)
+            one = cpu_baseline(w, args.cpu1_seconds, threads=1)
+            cpu["one_thread"] = {"value": one["value"], "unit": "GCUPS",
+                                 "pairs_per_s": one["pairs_per_s"], "sample": one["sample"]}
 
     rec = {
         "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,
@@ -243,9 +318,11 @@ def main():
         "forms": results,
         "cells_per_step": cells_per_step,
         "roofline": roofline,
+        "packed_tier": packed,
+        "c3": c3,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
-    store.close()
     print(json.dumps(rec), flush=True)
 
 

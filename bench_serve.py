@@ -25,8 +25,8 @@ sys.path.insert(0, ROOT)
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--rate", type=float, default=2000.0, help="requests per second")
-    ap.add_argument("--seconds", type=float, default=8.0, help="measured window")
-    ap.add_argument("--warmup", type=float, default=1.0, help="arrivals before the window")
+    ap.add_argument("--seconds", type=float, default=20.0, help="measured window")
+    ap.add_argument("--warmup", type=float, default=2.0, help="arrivals before the window")
     ap.add_argument("--max-size", type=int, default=10000)
     ap.add_argument("--workload", default="c5")
     ap.add_argument("--budget-mib", type=int, default=2048)
@@ -34,15 +34,23 @@ def main():
     ap.add_argument("--max-batch", type=int, default=65536)
     ap.add_argument("--seed", type=int, default=7)
     args = ap.parse_args()
-
-    import numpy as np
     import torch
-    import synth
-    import paper_2001_10049_amd as xd
-
     if not torch.cuda.is_available():
         print("needs a GPU", file=sys.stderr)
         sys.exit(2)
+    print(json.dumps(run(**{k: v for k, v in vars(args).items()})), flush=True)
+
+
+def run(rate=2000.0, seconds=20.0, warmup=2.0, max_size=10000, workload="c5", budget_mib=2048,
+        slots=4, max_batch=65536, seed=7) -> dict:
+    """One serving run; returns the JSON record."""
+    args = argparse.Namespace(rate=rate, seconds=seconds, warmup=warmup, max_size=max_size,
+                              workload=workload, budget_mib=budget_mib, slots=slots,
+                              max_batch=max_batch, seed=seed)
+    import numpy as np
+    import synth
+    import paper_2001_10049_amd as xd
+
     print("generating", args.workload, file=sys.stderr, flush=True)
     w = synth.config(args.workload)
     store = xd.ReadStore.from_workload(w)
@@ -121,7 +129,7 @@ def main():
                    % (args.max_size, args.rate, args.seconds)},
         "data": "synthetic",
     }
-    print(json.dumps(rec), flush=True)
+    return rec
 
 
 if __name__ == "__main__":
