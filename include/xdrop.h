@@ -311,6 +311,32 @@ int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, uint32_t bloo
                      uint64_t max_seeds, uint32_t* seeds, xd_overlap_counts* counts,
                      void* hip_stream);
 
+/* The same with the strand chosen (the paper does not discuss strand).
+ * strands = 1: forward k-mers, exactly xd_find_overlaps (rc may be NULL).
+ * strands = 2: both strands.  Each occurrence counts under its canonical
+ * k-mer, the smaller of its code and its reverse complement's (2 bits per
+ * base, first base highest; complement = 3 - code), so the count bounds
+ * apply to occurrences on either strand, with a strand bit that is 1 when
+ * the reverse complement is the smaller.  Two occurrences in different reads
+ * ra < rb with equal strand bits give the seed (pa, pb) of the forward pair
+ * (ra, rb, rc = 0); with different strand bits read rb matches the reverse
+ * complement of read ra there and they give the seed (pa, len(rb) - k - pb)
+ * of the pair (ra, rb, rc = 1): pb counted in the reverse complement of rb,
+ * as xd_align_pairs takes a pair with its rc flag set.  A k-mer equal to its
+ * own reverse complement (even k only) has strand bit 0.  Pairs are distinct
+ * (ra, rb, rc) sorted that way (one read pair may appear with both flags);
+ * seeds increase within a pair.  Extra output:
+ *   rc       uint8[max_pairs]         device; pair q's flag, written beside
+ *                                     pairs (required when strands = 2 and
+ *                                     outputs are written)
+ * strands outside {1, 2}, or strands = 2 with pairs given and rc NULL ->
+ * XD_EINVAL.  Everything else as xd_find_overlaps. */
+int xd_find_overlaps_strands(const xd_store* store, int32_t k, uint32_t m, uint32_t bloom_bits,
+                             uint64_t table_slots, int32_t strands, uint64_t max_pairs,
+                             uint32_t* pairs, uint8_t* rc, uint64_t* seed_off,
+                             uint64_t max_seeds, uint32_t* seeds, xd_overlap_counts* counts,
+                             void* hip_stream);
+
 /* Banded Smith-Waterman with the alignment itself: xd_banded_batch's
  * score, end, status and cells, plus the begin cell and the alignment path by
  * the textbook traceback (a reading; the paper gives no alignment output):

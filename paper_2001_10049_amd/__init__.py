@@ -228,36 +228,40 @@ def banded_traceback(store: ReadStore, pairs, seeds, w=None, w_scalar=32, k=17, 
 
 
 def find_overlaps(store: ReadStore, k=17, m=8, bloom_bits=0, capacity=None, stream=None,
-                  table_slots=0):
-    """Candidate read pairs sharing a retained k-mer (xd_find_overlaps).
+                  table_slots=0, strands=1):
+    """Candidate read pairs sharing a retained k-mer (xd_find_overlaps_strands).
 
-    capacity: (max_pairs, max_seeds) to allocate at once; None asks the
-    library for the counts first (one extra run).  bloom_bits and
-    table_slots size the first filter and the first hash table (0: the
-    library's choice); they change speed and memory, never the result.
-    Returns dict(pairs int32
-    [P, 2], seed_off int64 [P + 1], seeds int32 [S, 2] device tensors, counts
-    dict) or raises XdropError(XD_EAGAIN) when capacity is too small."""
+    strands: 1 = forward k-mers; 2 = canonical k-mers over both strands,
+    with a reverse-strand flag per pair.  capacity: (max_pairs, max_seeds) to
+    allocate at once; None asks the library for the counts first (one extra
+    run).  bloom_bits and table_slots size the first filter and the first
+    hash table (0: the library's choice); they change speed and memory, never
+    the result.  Returns dict(pairs int32 [P, 2], rc uint8 [P], seed_off
+    int64 [P + 1], seeds int32 [S, 2] device tensors, counts dict) or raises
+    XdropError(XD_EAGAIN) when capacity is too small."""
     import torch
     lib = _lib.load()
     cnt = _lib.OverlapCounts()
     st = _stream_ptr(stream)
     if capacity is None:
-        _lib.check(lib.xd_find_overlaps(store.handle, int(k), int(m), int(bloom_bits),
-                                        int(table_slots), 0, None, None, 0, None,
-                                        ctypes.byref(cnt), st))
+        _lib.check(lib.xd_find_overlaps_strands(store.handle, int(k), int(m), int(bloom_bits),
+                                                int(table_slots), int(strands), 0, None, None,
+                                                None, 0, None, ctypes.byref(cnt), st))
         capacity = (cnt.pairs, cnt.seeds)
     max_pairs, max_seeds = int(capacity[0]), int(capacity[1])
     dev = torch.device("cuda", torch.cuda.current_device())
     pairs = torch.empty((max(max_pairs, 1), 2), dtype=torch.int32, device=dev)
+    rc = torch.zeros(max(max_pairs, 1), dtype=torch.uint8, device=dev)
     seed_off = torch.empty(max_pairs + 1, dtype=torch.int64, device=dev)
     seeds = torch.empty((max(max_seeds, 1), 2), dtype=torch.int32, device=dev)
-    _lib.check(lib.xd_find_overlaps(store.handle, int(k), int(m), int(bloom_bits),
-                                    int(table_slots), max_pairs, _p(pairs), _p(seed_off),
-                                    max_seeds, _p(seeds), ctypes.byref(cnt), st))
+    _lib.check(lib.xd_find_overlaps_strands(store.handle, int(k), int(m), int(bloom_bits),
+                                            int(table_slots), int(strands), max_pairs,
+                                            _p(pairs), _p(rc), _p(seed_off), max_seeds,
+                                            _p(seeds), ctypes.byref(cnt), st))
     counts = {f: int(getattr(cnt, f)) for f, _ in _lib.OverlapCounts._fields_}
     P, S = counts["pairs"], counts["seeds"]
-    return dict(pairs=pairs[:P], seed_off=seed_off[:P + 1], seeds=seeds[:S], counts=counts)
+    return dict(pairs=pairs[:P], rc=rc[:P], seed_off=seed_off[:P + 1], seeds=seeds[:S],
+                counts=counts)
 
 
 def align_pairs(store: ReadStore, pairs, seed_off, seeds, rc=None, x=None, x_scalar=0,

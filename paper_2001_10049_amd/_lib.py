@@ -29,7 +29,7 @@ EXPORTS = (
     "xd_store_info", "xd_align_batch", "xd_align_batch_noalloc", "xd_batch_scratch_bytes",
     "xd_align_batch_persistent",
     "xd_align_pairs",
-    "xd_banded_batch", "xd_banded_traceback", "xd_find_overlaps",
+    "xd_banded_batch", "xd_banded_traceback", "xd_find_overlaps", "xd_find_overlaps_strands",
     "xd_plan_create",
     "xd_plan_launch", "xd_plan_destroy", "xd_profile_enable", "xd_profile_read",
     "xd_server_request_bytes", "xd_server_fixed_bytes", "xd_server_create", "xd_server_submit", "xd_server_poll",
@@ -139,6 +139,9 @@ def load() -> ctypes.CDLL:
     lib.xd_find_overlaps.argtypes = [vp, i32, u32, u32, u64, u64, vp, vp, u64, vp,
                                      ctypes.POINTER(OverlapCounts), vp]
     lib.xd_find_overlaps.restype = ctypes.c_int
+    lib.xd_find_overlaps_strands.argtypes = [vp, i32, u32, u32, u64, i32, u64, vp, vp, vp, u64,
+                                             vp, ctypes.POINTER(OverlapCounts), vp]
+    lib.xd_find_overlaps_strands.restype = ctypes.c_int
     lib.xd_plan_create.argtypes = batch + [ctypes.POINTER(Tuning), ctypes.POINTER(vp)]
     lib.xd_plan_create.restype = ctypes.c_int
     lib.xd_plan_launch.argtypes = [vp, vp]

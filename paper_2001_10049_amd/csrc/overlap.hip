@@ -76,10 +76,15 @@ struct KmerScan {
   uint32_t n_reads;
   int32_t k;
   uint64_t kmask;             // 2k low bits
+  int32_t both;               // 1: canonical k-mers (both strands)
 };
 
-// calls f(read, pos, code) for each k-mer start in chunk c, in increasing pos;
-// code packs the k bases 2 bits each, the first base highest
+// calls f(read, pos, code, strand) for each k-mer start in chunk c, in
+// increasing pos; code packs the k bases 2 bits each, the first base highest.
+// Forward strand only: the k-mer's code, strand 0.  Both strands: the
+// smaller of the code and its reverse complement's code (the complement
+// 3 - b of each base, in reverse order), strand 1 when the reverse
+// complement is the smaller.
 template <class F>
 __device__ __forceinline__ void for_kmers(const KmerScan& s, uint64_t c, F&& f) {
   uint32_t lo = 0, hi = s.n_reads - 1;  // the last read whose first chunk is <= c
@@ -101,11 +106,19 @@ __device__ __forceinline__ void for_kmers(const KmerScan& s, uint64_t c, F&& f) 
     }
     return (wv >> ((q & 15) * 2)) & 3u;
   };
-  uint64_t code = 0;
-  for (uint32_t q = p0; q + 1 < p0 + (uint32_t)s.k; ++q) code = (code << 2) | base(q);
+  const uint32_t top = 2u * (uint32_t)(s.k - 1);  // bit of a reverse-complement k-mer's last base
+  uint64_t code = 0, rcode = 0;
+  for (uint32_t q = p0; q + 1 < p0 + (uint32_t)s.k; ++q) {
+    const uint64_t b = base(q);
+    code = (code << 2) | b;
+    rcode = (rcode >> 2) | ((3ull - b) << top);
+  }
   for (uint32_t p = p0; p < p1; ++p) {
-    code = ((code << 2) | base(p + (uint32_t)s.k - 1)) & s.kmask;
-    f(r, p, code);
+    const uint64_t b = base(p + (uint32_t)s.k - 1);
+    code = ((code << 2) | b) & s.kmask;
+    rcode = (rcode >> 2) | ((3ull - b) << top);
+    const bool flip = s.both && rcode < code;
+    f(r, p, flip ? rcode : code, flip ? 1u : 0u);
   }
 }
 
@@ -126,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_bloom(KmerScan s, unsigned long lo
   const uint64_t c = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
   uint32_t rep = 0, fresh = 0;
   if (c < s.n_chunks) {
-    for_kmers(s, c, [&](uint32_t, uint32_t, uint64_t code) {
+    for_kmers(s, c, [&](uint32_t, uint32_t, uint64_t code, uint32_t) {
       const uint64_t h = fmix64(code);
       const unsigned long long bits = bloom_bits(h);
       const unsigned long long old = atomicOr(&A[bloom_word(h, WA)], bits);
@@ -168,7 +181,7 @@ __global__ __launch_bounds__(kThreads) void k_table(KmerScan s, const unsigned l
                                                     unsigned long long* ctr) {
   const uint64_t c = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
   if (c >= s.n_chunks) return;
-  for_kmers(s, c, [&](uint32_t r, uint32_t p, uint64_t code) {
+  for_kmers(s, c, [&](uint32_t r, uint32_t p, uint64_t code, uint32_t strand) {
     const uint64_t h2 = fmix64(code ^ kSaltB);
     const unsigned long long bits = bloom_bits(h2);
     if ((B[bloom_word(h2, WB)] & bits) != bits) return;
@@ -188,7 +201,7 @@ __global__ __launch_bounds__(kThreads) void k_table(KmerScan s, const unsigned l
       slot = (slot + 1) & (t.cap - 1);
     }
     const uint32_t i = atomicAdd(&t.cnt[slot], 1u);
-    if (i < t.m) t.loc[slot * t.m + i] = make_uint2(r, p);
+    if (i < t.m) t.loc[slot * t.m + i] = make_uint2(r, p | strand << 31);
   });
 }
 
@@ -255,9 +268,14 @@ __global__ __launch_bounds__(kThreads) void k_retain_write(Table t, const uint64
   }
 }
 
-// one thread per retained k-mer: its seeds (ra, rb, pa, pb) with ra < rb
+// one thread per retained k-mer: its seeds (ra, rb, rc << sbit | pa, pb) with
+// ra < rb.  rc = the two occurrences' strand bits differ: read rb matches the
+// reverse complement of read ra there, and pb counts in that reverse
+// complement (len[rb] - k - its position in rb).  sbit is above every
+// position, so the sort orders a pair's forward seeds before its reverse ones.
 __global__ __launch_bounds__(kThreads) void k_emit(Table t, const uint32_t* ret, uint64_t n_ret,
-                                                   const uint64_t* pair_off, uint4* items) {
+                                                   const uint64_t* pair_off, const uint32_t* len,
+                                                   int32_t k, uint32_t sbit, uint4* items) {
   const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n_ret) return;
   const uint64_t s = ret[i];
@@ -269,7 +287,11 @@ __global__ __launch_bounds__(kThreads) void k_emit(Table t, const uint32_t* ret,
     for (uint32_t y = x + 1; y < c; ++y) {
       const uint2 b = L[y];
       if (a.x == b.x) continue;
-      items[o++] = a.x < b.x ? make_uint4(a.x, b.x, a.y, b.y) : make_uint4(b.x, a.x, b.y, a.y);
+      const uint2 lo = a.x < b.x ? a : b, hi = a.x < b.x ? b : a;
+      const uint32_t rc = (lo.y ^ hi.y) >> 31;
+      const uint32_t pa = lo.y & 0x7fffffffu, p_hi = hi.y & 0x7fffffffu;
+      const uint32_t pb = rc ? len[hi.x] - (uint32_t)k - p_hi : p_hi;
+      items[o++] = make_uint4(lo.x, hi.x, rc << sbit | pa, pb);
     }
   }
 }
@@ -345,16 +367,20 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint4* in, uint
 
 // ---- output -------------------------------------------------------------------
 
+// a new pair starts where (ra, rb, rc) changes
 __global__ __launch_bounds__(kThreads) void k_heads(const uint4* items, uint64_t n,
-                                                    uint32_t* flag) {
+                                                    uint32_t sbit, uint32_t* flag) {
   const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
-  flag[i] = i == 0 || items[i].x != items[i - 1].x || items[i].y != items[i - 1].y;
+  flag[i] = i == 0 || items[i].x != items[i - 1].x || items[i].y != items[i - 1].y ||
+            (items[i].z >> sbit) != (items[i - 1].z >> sbit);
 }
 
-// head[] is the exclusive scan of the head flags (n + 1 entries)
+// head[] is the exclusive scan of the head flags (n + 1 entries); rc may be
+// null (forward strand only)
 __global__ __launch_bounds__(kThreads) void k_csr(const uint4* items, uint64_t n,
-                                                  const uint32_t* head, uint32_t* pairs,
+                                                  const uint32_t* head, uint32_t sbit,
+                                                  uint32_t* pairs, uint8_t* rc,
                                                   uint64_t* seed_off, uint32_t* seeds) {
   const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
@@ -363,9 +389,10 @@ __global__ __launch_bounds__(kThreads) void k_csr(const uint4* items, uint64_t n
   if (head[i + 1] != p) {
     pairs[2 * (uint64_t)p] = v.x;
     pairs[2 * (uint64_t)p + 1] = v.y;
+    if (rc) rc[p] = (uint8_t)(v.z >> sbit);
     seed_off[p] = i;
   }
-  seeds[2 * i] = v.z;
+  seeds[2 * i] = v.z & ((1u << sbit) - 1u);
   seeds[2 * i + 1] = v.w;
   if (i == 0) seed_off[head[n]] = n;
 }
@@ -408,11 +435,14 @@ uint32_t bit_length(uint64_t v) { return v ? 64u - (uint32_t)__builtin_clzll(v) 
 
 }  // namespace
 
-extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, uint32_t bloom_bits,
-                                uint64_t table_slots, uint64_t max_pairs, uint32_t* pairs,
-                                uint64_t* seed_off,
-                                uint64_t max_seeds, uint32_t* seeds, xd_overlap_counts* counts,
-                                void* hip_stream) {
+namespace {
+
+int find_overlaps(const xd_store* store, int32_t k, uint32_t m, uint32_t bloom_bits,
+                  uint64_t table_slots, int32_t strands, uint64_t max_pairs, uint32_t* pairs,
+                  uint8_t* rc_out, uint64_t* seed_off, uint64_t max_seeds, uint32_t* seeds,
+                  xd_overlap_counts* counts, void* hip_stream) {
+  if (strands != 1 && strands != 2)
+    return fail(XD_EINVAL, "xd_find_overlaps: strands must be 1 or 2 (got %d)", strands);
   StoreView sv;
   int rc = xd_internal_store_view(store, &sv);
   if (rc) return rc;
@@ -428,6 +458,9 @@ extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, ui
   if (write && !(pairs && seed_off && seeds))
     return fail(XD_EINVAL, "xd_find_overlaps: pairs, seed_off and seeds must all be given or "
                            "all be NULL");
+  if (write && strands == 2 && !rc_out)
+    return fail(XD_EINVAL, "xd_find_overlaps: both strands need the rc output");
+  if (strands == 1) rc_out = nullptr;
   hipStream_t st = (hipStream_t)hip_stream;
   xd_overlap_counts cn = {};
   // one call at a time per device: its buffers come from the device's cache
@@ -468,7 +501,7 @@ extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, ui
     OV_TRY(hipMemsetAsync(B, 0, WB * 8, st));
     OV_TRY(hipMemsetAsync(ctr, 0, 4 * 8, st));
     KmerScan ks{sv.words, sv.word_off, sv.len, d_chunk, n_chunks, sv.n_reads, k,
-                k == 32 ? ~0ull : (1ull << (2 * k)) - 1};
+                k == 32 ? ~0ull : (1ull << (2 * k)) - 1, strands == 2 ? 1 : 0};
     hipLaunchKernelGGL(k_bloom, dim3(grid_for(n_chunks, kThreads)), dim3(kThreads), 0, st, ks, A,
                        WA, B, WB, ctr);
     hipLaunchKernelGGL(k_popcount, dim3(grid_for(WB, kThreads * 16)), dim3(kThreads), 0, st, B,
@@ -550,13 +583,14 @@ extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, ui
       uint4 *cur = nullptr, *alt = nullptr;
       OV_TRY(ar.get(&cur, S));
       OV_TRY(ar.get(&alt, S));
-      hipLaunchKernelGGL(k_emit, dim3(grid_for(cn.retained, kThreads)), dim3(kThreads), 0, st, t,
-                         ret, cn.retained, npair, cur);
-      // keys (ra, rb, pa, pb): least significant field first
+      // positions take bits_p bits; the strand flag sits just above them
       const uint32_t bits_r = bit_length(sv.n_reads ? sv.n_reads - 1 : 0);
       const uint32_t bits_p = bit_length(sv.max_len);
+      hipLaunchKernelGGL(k_emit, dim3(grid_for(cn.retained, kThreads)), dim3(kThreads), 0, st, t,
+                         ret, cn.retained, npair, sv.len, k, bits_p, cur);
+      // keys (ra, rb, rc, pa, pb): least significant field first
       const int fields[4] = {3, 2, 1, 0};
-      const uint32_t fbits[4] = {bits_p, bits_p, bits_r, bits_r};
+      const uint32_t fbits[4] = {bits_p, bits_p + (strands == 2 ? 1u : 0u), bits_r, bits_r};
       const uint32_t nt = grid_for(S, kSortTile);
       uint32_t* hist = nullptr;
       OV_TRY(ar.get(&hist, (uint64_t)nt * 256 + 1));
@@ -574,14 +608,14 @@ extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, ui
       uint32_t* head = nullptr;
       OV_TRY(ar.get(&head, S + 1));
       hipLaunchKernelGGL(k_heads, dim3(grid_for(S, kThreads)), dim3(kThreads), 0, st, cur, S,
-                         head);
+                         bits_p, head);
       OV_TRY(xscan::exclusive_scan<uint32_t>(ar, head, head, S));
       uint32_t P = 0;
       if ((rc = fetch(st, head + S, &P))) return rc;
       cn.pairs = P;
       if (write && cn.pairs <= max_pairs && cn.seeds <= max_seeds)
         hipLaunchKernelGGL(k_csr, dim3(grid_for(S, kThreads)), dim3(kThreads), 0, st, cur, S,
-                           head, pairs, seed_off, seeds);
+                           head, bits_p, pairs, rc_out, seed_off, seeds);
     }
   }
   if (counts) *counts = cn;
@@ -594,6 +628,26 @@ extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, ui
   if (le != hipSuccess) return hip_fail(le, "kernel launch");
   OV_TRY(hipStreamSynchronize(st));
   return XD_OK;
+}
+
+}  // namespace
+
+extern "C" int xd_find_overlaps(const xd_store* store, int32_t k, uint32_t m, uint32_t bloom_bits,
+                                uint64_t table_slots, uint64_t max_pairs, uint32_t* pairs,
+                                uint64_t* seed_off, uint64_t max_seeds, uint32_t* seeds,
+                                xd_overlap_counts* counts, void* hip_stream) {
+  return find_overlaps(store, k, m, bloom_bits, table_slots, 1, max_pairs, pairs, nullptr,
+                       seed_off, max_seeds, seeds, counts, hip_stream);
+}
+
+extern "C" int xd_find_overlaps_strands(const xd_store* store, int32_t k, uint32_t m,
+                                        uint32_t bloom_bits, uint64_t table_slots,
+                                        int32_t strands, uint64_t max_pairs, uint32_t* pairs,
+                                        uint8_t* rc, uint64_t* seed_off, uint64_t max_seeds,
+                                        uint32_t* seeds, xd_overlap_counts* counts,
+                                        void* hip_stream) {
+  return find_overlaps(store, k, m, bloom_bits, table_slots, strands, max_pairs, pairs, rc,
+                       seed_off, max_seeds, seeds, counts, hip_stream);
 }
 
 // frees the stage's kept buffers on every device (for xd_release_memory)

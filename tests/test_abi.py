@@ -114,6 +114,16 @@ def test_find_overlaps_rejects_null_store():
     assert rc == _lib.XD_EINVAL and b"store" in lib.xd_last_error()
 
 
+def test_find_overlaps_strands_rejects_bad_strand():
+    lib = _lib.load()
+    cnt = _lib.OverlapCounts()
+    for strands in (0, 3, -1):
+        # the dummy store is never dereferenced: the strand is checked first
+        rc = lib.xd_find_overlaps_strands(ctypes.c_void_p(1), 17, 8, 0, 0, strands, 0, None,
+                                          None, None, 0, None, ctypes.byref(cnt), None)
+        assert rc == _lib.XD_EINVAL and b"strands" in lib.xd_last_error()
+
+
 def test_banded_traceback_argument_errors_without_device():
     lib = _lib.load()
     dummy = ctypes.c_void_p(1)  # never dereferenced: scalar checks come first

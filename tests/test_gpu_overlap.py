@@ -210,3 +210,105 @@ def test_c2_candidates_align_like_the_oracle():
     for f in ("beg", "end"):
         assert np.array_equal(got[f][idx].view(np.uint32), ref[f].astype(np.uint32)), f
     assert np.array_equal(got["cells"][idx].astype(np.uint64), ref["cells"].astype(np.uint64))
+
+
+# ---- both strands ----------------------------------------------------------------
+
+def _revcomp(s):
+    return (3 - np.asarray(s, np.uint8)[::-1]).astype(np.uint8)
+
+
+def gpu2(codes, off, length, k, m, bloom_bits=0):
+    with xd.ReadStore(codes, off, length) as st:
+        r = xd.find_overlaps(st, k=k, m=m, bloom_bits=bloom_bits, strands=2)
+    torch.cuda.synchronize()
+    return (r["pairs"].cpu().numpy().view(np.uint32).reshape(-1, 2),
+            r["seed_off"].cpu().numpy().view(np.uint64),
+            r["seeds"].cpu().numpy().view(np.uint32).reshape(-1, 2), r["counts"],
+            r["rc"].cpu().numpy())
+
+
+def assert_same2(got, ref, label):
+    assert_same(got, ref, label)
+    assert np.array_equal(got[4], ref[4]), "%s: rc differs" % label
+
+
+def test_both_strands_small_sets_match_oracle():
+    rng = np.random.default_rng(22)
+    for trial in range(30):
+        base = rng.integers(0, 4, 3000).astype(np.uint8)
+        seqs = []
+        for _ in range(int(rng.integers(1, 30))):
+            n = int(rng.integers(0, 500))
+            s = int(rng.integers(0, 3000 - n + 1))
+            r = base[s:s + n].copy()
+            flip = rng.random(n) < 0.04
+            r[flip] = rng.integers(0, 4, int(flip.sum()))
+            seqs.append(_revcomp(r) if rng.random() < 0.5 else r)
+        if trial % 5 == 0:
+            seqs.append(np.tile(np.array([0, 1, 2, 3], np.uint8), 30))  # ACGT...: palindromes
+        k = int(rng.choice([1, 2, 4, 5, 11, 17, 31]))
+        m = int(rng.choice([2, 3, 8, 64]))
+        codes, off, length = _reads(seqs)
+        ref = ov.find_overlaps(codes, off, length, k, 2, m, strands=2)
+        got = gpu2(codes, off, length, k, m)
+        assert_same2(got, ref, "trial %d (k=%d, m=%d, %d reads)" % (trial, k, m, len(seqs)))
+
+
+def flipped_c2_small():
+    """The c2-small read set with every other read stored reverse-complemented."""
+    w = synth.config("c2-small")
+    seqs = [w.read(r).copy() for r in range(w.n_reads)]
+    seqs = [_revcomp(s) if r % 2 else s for r, s in enumerate(seqs)]
+    return _reads(seqs)
+
+
+def test_both_strands_on_opposite_strand_read_set():
+    codes, off, length = flipped_c2_small()
+    ref = ov.find_overlaps_sorted(codes, off, length, 17, 2, 8, strands=2)
+    assert ref[4].sum() > 0.3 * ref[4].size      # opposite-strand pairs are common
+    for bits in (0, 4):
+        got = gpu2(codes, off, length, 17, 8, bloom_bits=bits)
+        assert_same2(got, ref, "flipped c2-small bloom_bits=%d" % bits)
+    # forward k-mers alone miss the opposite-strand overlaps
+    fwd = gpu(codes, off, length, 17, 8)
+    assert fwd[3]["pairs"] < ref[0].shape[0]
+    # strands = 1 through the new entry point is the forward-only call
+    with xd.ReadStore(codes, off, length) as st:
+        r1 = xd.find_overlaps(st, k=17, m=8, strands=1)
+        torch.cuda.synchronize()
+        assert np.array_equal(r1["pairs"].cpu().numpy().view(np.uint32).reshape(-1, 2), fwd[0])
+        assert np.array_equal(r1["seeds"].cpu().numpy().view(np.uint32).reshape(-1, 2), fwd[2])
+        assert int(r1["rc"].sum()) == 0
+
+
+def test_both_strands_pairs_feed_alignment():
+    # candidate pairs from both strands, aligned with their strand flags, on
+    # a sample of pairs against the pair oracle
+    codes, off, length = flipped_c2_small()
+    with xd.ReadStore(codes, off, length) as st:
+        r = xd.find_overlaps(st, k=17, m=8, strands=2)
+        P = r["counts"]["pairs"]
+        out = xd.align_pairs(st, r["pairs"], r["seed_off"], r["seeds"], rc=r["rc"],
+                             x_scalar=25, min_dist=17, max_seeds=1, k=17,
+                             n_seeds=r["counts"]["seeds"])
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        so = r["seed_off"].cpu().numpy()
+        pairs_h = r["pairs"].cpu().numpy()
+        seeds_h = r["seeds"].cpu().numpy()
+        rc_h = r["rc"].cpu().numpy()
+    assert (got["status"] == 0).all()
+    idx = np.linspace(0, P - 1, 60).astype(np.int64)
+    idx = np.unique(np.concatenate([idx, np.flatnonzero(rc_h)[:30]]))
+    sub_off = np.concatenate([[0], np.cumsum(so[idx + 1] - so[idx])]).astype(np.uint64)
+    sub_seeds = np.concatenate([seeds_h[so[i]:so[i + 1]] for i in idx])
+    ref = opairs.align_pairs(codes, off, length, pairs_h[idx], sub_off, sub_seeds,
+                             rc=rc_h[idx], x_scalar=25, min_dist=17, max_seeds=1, k=17)
+    for f in ("score", "status", "seed_idx", "n_kept"):
+        assert np.array_equal(got[f][idx], ref[f]), f
+    for f in ("beg", "end"):
+        assert np.array_equal(got[f][idx].astype(np.uint32), ref[f].astype(np.uint32)), f
+    assert np.array_equal(got["cells"][idx].astype(np.uint64), ref["cells"].astype(np.uint64))
+    # true opposite-strand overlaps align over kilobases
+    assert got["score"][rc_h == 1].max() > 1000
