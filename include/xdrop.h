@@ -478,6 +478,9 @@ typedef struct {
   double ms_wide;         /* summed time of the wider windows and the band tier */
   double ms_combine;      /* summed time of the combine kernel */
   double ms_total;        /* first to last event, summed over calls */
+  uint64_t resumed;       /* of the moves to a wider window (to_tier2 .. to_tier5), those that
+                             carried the extension's state and resumed where it stopped (the
+                             others re-ran from the seed: no room left for states) */
 } xd_profile;
 
 int xd_profile_enable(int on);

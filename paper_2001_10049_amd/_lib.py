@@ -78,7 +78,8 @@ class Profile(ctypes.Structure):
                 ("to_tier4", ctypes.c_uint64), ("to_tier5", ctypes.c_uint64),
                 ("to_band", ctypes.c_uint64),
                 ("ms_tier1", ctypes.c_double), ("ms_wide", ctypes.c_double),
-                ("ms_combine", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_combine", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("resumed", ctypes.c_uint64)]
 
 
 class XdropError(RuntimeError):

@@ -135,6 +135,19 @@ BandGeom band_geom(uint32_t max_len, uint32_t blocks) {
 
 uint64_t band_bytes(const BandGeom& b) { return (uint64_t)b.blocks * 12ull * (uint64_t)b.cap; }
 
+// Resume states: an extension that overflows window t (64 << t rows, t < 4)
+// into the next one leaves its state (xd::ResumeHead and two int32 rows per
+// window row) in slot s of pool t when its overflow-list slot s is below the
+// pool's capacity, and marks its list entry with kResumeFlag; past that the
+// next window re-runs it from its seed.  Capacities: 2n / kResumeDiv[t]
+// extensions (the share of extensions expected to outgrow window t).
+constexpr uint32_t kResumeFlag = 0x80000000u;
+constexpr uint32_t kResumeDiv[4] = {8, 16, 32, 256};
+constexpr uint64_t resume_rec(int t) { return xd::resume_bytes(64 << t); }
+uint32_t resume_cap(uint64_t n, int t) {
+  return (uint32_t)((2 * n + kResumeDiv[t] - 1) / kResumeDiv[t]);
+}
+
 // Device scratch of one batch.
 struct Scratch {
   ExtOut* ext;        // [2n]
@@ -143,6 +156,8 @@ struct Scratch {
   uint32_t* hist;     // [kBins] histogram, then running cursors
   uint32_t* ctr;      // [32] counters, see below
   void* targs;        // [6] TierArgs of the five windows and the band tier
+  uint8_t* state[4];  // resume states of windows 0..3 (resume_cap x resume_rec)
+  uint32_t state_cap[4];
   int32_t* band;      // [blocks][3][cap] rows of the band tier
   BandGeom geom;
 };
@@ -151,16 +166,23 @@ constexpr int kOvfCount = 0;   // [0..4] sizes of ovf[0..4]
 constexpr int kHead = 5;       // [5..9] work heads of tiers 0..4
 constexpr int kSeg = 10;       // [10..14] queue start of segments 0..3, then 2n
 constexpr int kBandHead = 15;  // work head of the band tier
+constexpr int kResumed = 16;   // [16..19] moves out of windows 0..3 that carried their state
 constexpr int kCtrWords = 32;
 constexpr int kTierArgsBytes = 6 * 256;  // >= 6 * sizeof(TierArgs), checked below
 constexpr uint64_t kFixedBytes = (kBins * 4 + kCtrWords * 4 + kTierArgsBytes + 255) & ~255ull;
+
+uint64_t state_bytes(uint64_t n, int t) {
+  return ((uint64_t)resume_cap(n, t) * resume_rec(t) + 255) & ~255ull;
+}
 
 // scratch of a batch of n tasks without the band tier's rows
 uint64_t task_scratch_bytes(uint64_t n) {
   const uint64_t n_ext = 2 * n;
   const uint64_t ext = (n_ext * sizeof(ExtOut) + 255) & ~255ull;
   const uint64_t list = (n_ext * 4 + 255) & ~255ull;
-  return ext + 6 * list + kFixedBytes;
+  uint64_t st = 0;
+  for (int t = 0; t < 4; ++t) st += state_bytes(n, t);
+  return ext + 6 * list + kFixedBytes + st;
 }
 
 uint64_t scratch_bytes(uint64_t n, const BandGeom& g) {
@@ -179,7 +201,13 @@ Scratch scratch_carve(char* base, uint64_t n, const BandGeom& g) {
   s.hist = (uint32_t*)fixed;
   s.ctr = (uint32_t*)(fixed + kBins * 4);
   s.targs = fixed + kBins * 4 + kCtrWords * 4;
-  s.band = (int32_t*)(fixed + kFixedBytes);
+  uint8_t* st = (uint8_t*)(fixed + kFixedBytes);
+  for (int t = 0; t < 4; ++t) {
+    s.state[t] = st;
+    s.state_cap[t] = resume_cap(n, t);
+    st += state_bytes(n, t);
+  }
+  s.band = (int32_t*)st;
   s.geom = g;
   return s;
 }
@@ -194,6 +222,9 @@ struct TierArgs {
   uint32_t* head;
   uint32_t* out_list;       // overflow into the next tier, or null
   uint32_t* out_count;
+  const uint8_t* in_state;  // resume states of in_list's flagged entries
+  uint8_t* out_state;       // where this tier leaves states (null: none)
+  uint32_t in_rec, out_rec, out_cap, pad;
 };
 
 static_assert(xd::kBandedMaxW == XD_BAND_MAX, "band limit");
@@ -275,10 +306,46 @@ __device__ __forceinline__ bool make_ext(const BatchArgs& A, uint32_t e, xd::Ext
   return true;
 }
 
-// Sets up and runs extension e on the calling wave.  Returns false if it
-// overflowed this tier's window.
-template <int CPL, int GS, bool UNIT>
-__device__ __forceinline__ bool run_ext(const BatchArgs& A, uint32_t e, uint32_t* ring) {
+__device__ __forceinline__ void push_list(uint32_t* list, uint32_t* count, uint32_t e) {
+  if (xd::lane_id() == 0) {
+    const uint32_t slot = atomicAdd(count, 1u);
+    list[slot] = e;
+  }
+}
+
+// Extension e overflowed its window (its state, when the window saves one,
+// at the start of ring): it goes on list, the next window's work; when its
+// slot has room in pool (cap states of rec bytes) the state is copied there
+// and the entry marked with kResumeFlag.  A null list means there is no
+// wider window: the extension is marked unresolved.
+__device__ __forceinline__ void overflow_to(ExtOut* ext, uint32_t* list, uint32_t* count,
+                                            uint8_t* pool, uint32_t cap, uint32_t rec,
+                                            uint32_t e, const uint32_t* ring) {
+  if (!list) {
+    if (xd::lane_id() == 0) {
+      ExtOut o = {0, 0, 0, xd::kExtOverflow, 0};
+      ext[e] = o;
+    }
+    return;
+  }
+  uint32_t slot = 0;
+  if (xd::lane_id() == 0) slot = atomicAdd(count, 1u);
+  slot = __builtin_amdgcn_readfirstlane(__shfl(slot, 0, 64));
+  const bool keep = pool && slot < cap;
+  if (keep) {
+    uint32_t* dst = (uint32_t*)(pool + (uint64_t)slot * rec);
+    for (uint32_t w = xd::lane_id(); w < rec / 4; w += 64) dst[w] = ring[w];
+    if (xd::lane_id() == 0) atomicAdd(count + (kResumed - kOvfCount), 1u);
+  }
+  if (xd::lane_id() == 0) list[slot] = e | (keep ? kResumeFlag : 0u);
+}
+
+// Sets up and runs extension e on the calling wave, from its seed or from a
+// narrower window's state (resume non-null).  Returns false if it overflowed
+// this tier's window (SAVE: its state is then at the start of ring).
+template <int CPL, int GS, bool UNIT, bool SAVE, bool RESUME>
+__device__ __forceinline__ bool run_ext(const BatchArgs& A, uint32_t e, uint32_t* ring,
+                                        const uint8_t* resume) {
   xd::Ext ex;
   if (!make_ext(A, e, ex)) {
     if (xd::lane_id() == 0) {
@@ -288,16 +355,9 @@ __device__ __forceinline__ bool run_ext(const BatchArgs& A, uint32_t e, uint32_t
     return true;
   }
   ExtOut o;
-  if (!xd::extend<CPL, GS, UNIT>(ex, A.sc, ring, o)) return false;
+  if (!xd::extend<CPL, GS, UNIT, SAVE, RESUME>(ex, A.sc, ring, o, resume)) return false;
   if (xd::lane_id() == 0) A.ext[e] = o;
   return true;
-}
-
-__device__ __forceinline__ void push_list(uint32_t* list, uint32_t* count, uint32_t e) {
-  if (xd::lane_id() == 0) {
-    const uint32_t slot = atomicAdd(count, 1u);
-    list[slot] = e;
-  }
 }
 
 // zero the counters and the histogram (a kernel rather than a memset so that
@@ -313,11 +373,17 @@ __global__ __launch_bounds__(256) void k_reset(uint32_t* ctr, uint32_t* hist, Ti
 
 template <int CPL, int GS, bool UNIT>
 __global__ __launch_bounds__(64) void k_ext_first(BatchArgs A, uint32_t e0, uint32_t* ovf_list,
-                                                  uint32_t* ovf_count) {
+                                                  uint32_t* ovf_count, uint8_t* state,
+                                                  uint32_t state_cap) {
   __shared__ uint32_t ring[xd::Tier<CPL, GS>::LDS_WORDS];
   XD_STAMP_T0();
   const uint32_t e = e0 + blockIdx.x;
-  if (!run_ext<CPL, GS, UNIT>(A, e, ring)) push_list(ovf_list, ovf_count, e);
+  // no state: saving one costs this hot kernel about 4 % on c2, where no
+  // extension overflows; what outgrows 64 cells re-runs from its seed
+  (void)state;
+  (void)state_cap;
+  if (!run_ext<CPL, GS, UNIT, false, false>(A, e, ring, nullptr))
+    push_list(ovf_list, ovf_count, e);
   XD_STAMP(stamps::kFirst, 1u);
 }
 
@@ -350,19 +416,20 @@ __global__ __launch_bounds__(64 * WAVES) void k_ext_tier(const TierArgs* __restr
     if (xd::lane_id() == 0) idx = atomicAdd(Q.head, 1u);
     idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
     if (idx >= seg_len + n_in) break;
-    const uint32_t e = __builtin_amdgcn_readfirstlane(
+    const uint32_t raw = __builtin_amdgcn_readfirstlane(
         idx < seg_len ? Q.queue[seg_lo + idx] : Q.in_list[idx - seg_len]);
+    const uint32_t e = raw & ~kResumeFlag;
+    const uint8_t* resume =
+        raw & kResumeFlag ? Q.in_state + (uint64_t)(idx - seg_len) * Q.in_rec : nullptr;
 #ifdef XD_WAVE_STAMPS
     ++taken;
 #endif
-    if (!run_ext<CPL, GS, UNIT>(Q.A, e, rings[w])) {
+    // the 64-cell windows neither leave nor take states (the 128-cell window
+    // receives none), the widest leaves none (the band tier re-runs it)
+    if (!run_ext<CPL, GS, UNIT, (CPL >= 2 && CPL < 16), (CPL >= 4)>(Q.A, e, rings[w], resume)) {
       const TierArgs& R = *pp;
-      if (R.out_list) {
-        push_list(R.out_list, R.out_count, e);
-      } else if (xd::lane_id() == 0) {
-        ExtOut o = {0, 0, 0, xd::kExtOverflow, 0};
-        R.A.ext[e] = o;
-      }
+      overflow_to(R.A.ext, R.out_list, R.out_count, R.out_state, R.out_cap, R.out_rec, e,
+                  rings[w]);
     }
   }
   XD_STAMP(stamps::kTier + CPL, taken);
@@ -458,7 +525,7 @@ __global__ __launch_bounds__(64 * kBandWaves) void k_ext_band(const TierArgs* __
     if (threadIdx.x == 0) {
       const uint32_t n_in = *Q.in_count;
       const uint32_t idx = atomicAdd(Q.head, 1u);
-      item = idx < n_in ? Q.in_list[idx] : 0xffffffffu;
+      item = idx < n_in ? Q.in_list[idx] & ~kResumeFlag : 0xffffffffu;
     }
     __syncthreads();
     const uint32_t e = item;
@@ -1010,6 +1077,17 @@ TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
   p.t[4] = {A, S.queue, nullptr, S.ovf[3], c + kOvfCount + 3, c + kHead + 4, S.ovf[4],
             c + kOvfCount + 4};
   p.t[5] = {A, S.queue, nullptr, S.ovf[4], c + kOvfCount + 4, c + kBandHead, nullptr, nullptr};
+  // resume states: window t leaves them in pool t, window t + 1 reads them;
+  // the band tier re-runs what outgrows the 1024-cell window
+  for (int t = 0; t < 6; ++t) {
+    TierArgs& T = p.t[t];
+    T.in_state = t >= 1 && t <= 4 ? S.state[t - 1] : nullptr;
+    T.in_rec = t >= 1 && t <= 4 ? (uint32_t)resume_rec(t - 1) : 0u;
+    T.out_state = t <= 3 ? S.state[t] : nullptr;
+    T.out_cap = t <= 3 ? S.state_cap[t] : 0u;
+    T.out_rec = t <= 3 ? (uint32_t)resume_rec(t) : 0u;
+    T.pad = 0;
+  }
   p.pz = pair_shared(A.sc);
   return p;
 }
@@ -1042,7 +1120,8 @@ void launch_plain_ext(const BatchArgs& A, const Scratch& S, uint64_t n_ext, hipE
   for (uint64_t e0 = 0; e0 < n_ext; e0 += kChunkBlocks) {
     const uint64_t nb = std::min<uint64_t>(kChunkBlocks, n_ext - e0);
     hipLaunchKernelGGL((k_ext_first<1, 16, UNIT>), dim3((uint32_t)nb), dim3(64), 0, stream, A,
-                       (uint32_t)e0, S.ovf[0], S.ctr + kOvfCount + 0);
+                       (uint32_t)e0, S.ovf[0], S.ctr + kOvfCount + 0, S.state[0],
+                       S.state_cap[0]);
   }
   if (ev) (void)hipEventRecord(ev[1], stream);
   launch_wide<UNIT>(S, kWideBlocks / 4, stream);
@@ -1904,6 +1983,7 @@ int xd_profile_read(xd_profile* out, int reset) {
     g_prof_sum.to_tier4 += r.counters[kOvfCount + 2];
     g_prof_sum.to_tier5 += r.counters[kOvfCount + 3];
     g_prof_sum.to_band += r.counters[kOvfCount + 4];
+    for (int t = 0; t < 4; ++t) g_prof_sum.resumed += r.counters[kResumed + t];
     g_prof_sum.ms_tier1 += t1;
     g_prof_sum.ms_wide += t2;
     g_prof_sum.ms_combine += t3;

@@ -225,6 +225,22 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
+// State of an extension that outgrew a window, for the next wider window to
+// resume from (instead of re-running it from its seed): the last antidiagonal
+// d, the window's first row, the threshold for d + 1 (and the total rebased
+// off it), the arg-max so far, the cells evaluated so far, then by row offset
+// q in [0, q_rows) the window's U on d and on d - 1 shifted up one row (row q
+// holds U_{d-1} of row q - 1, the diagonal neighbour), and top_prev = U_{d-1}
+// of the window's top row.  Dead cells are 0 as in the registers.
+struct ResumeHead {
+  int32_t d, base, thr, bi, dstar, top_prev, q_rows, pad;
+  int64_t rebased;
+  uint64_t cells;
+  uint32_t pad2[4];
+};
+static_assert(sizeof(ResumeHead) == 64, "resume header");
+constexpr uint64_t resume_bytes(int q_rows) { return 64ull + 8ull * (uint64_t)q_rows; }
+
 // Runs one extension on the calling wavefront.  Returns false on window
 // overflow (res untouched).  ring: LDS_WORDS words private to this wave.
 //
@@ -233,11 +249,21 @@ __device__ __forceinline__ void wave_lds_fence() {
 // group, and the group's ring values are read ahead of its first step.
 // UNIT: match == 1.  Then a cell of antidiagonal d scores at most T_{d-1} + 1,
 // so an improving cell is exactly T_{d-1} + 1 and no max-reduction is needed.
-template <int CPL, int GS, bool UNIT>
+//
+// resume: null, or the state a narrower window saved (ResumeHead + rows),
+// from which the extension continues.  SAVE: on overflow, leave the state
+// (resume_bytes(Q) bytes, the same layout) at the start of ring, for the
+// caller to keep; nothing the loop needs stays live for it but the window's
+// top row of the previous antidiagonal.
+// RESUME: compiled with the resume path (resume is ignored otherwise).
+template <int CPL, int GS, bool UNIT, bool SAVE = false, bool RESUME = false>
 __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
-                                       uint32_t* __restrict__ ring, ExtOut& res) {
+                                       uint32_t* __restrict__ ring, ExtOut& res,
+                                       const uint8_t* __restrict__ resume = nullptr) {
   using TI = Tier<CPL, GS>;
   constexpr int Q = TI::Q;
+  constexpr bool kSaves = SAVE;
+  static_assert(!SAVE || TI::LDS_WORDS * 4 >= resume_bytes(TI::Q), "state fits the ring");
   constexpr int kShort = GS < 4 ? GS : 4;  // group length near the window's top
   constexpr int RING = TI::RING;
   constexpr int MASK = RING - 1;
@@ -332,6 +358,7 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
   // the improvement threshold is thr + X
   int32_t thr = g + kBias0;
   int64_t rebased = 0;  // total taken off U and thr (kRebaseAt)
+  int32_t top_prev = 0;  // U of the window's top row on antidiagonal d - 1
   uint32_t cnt = 0;  // evaluated cells of this lane
   // a cell's match bonus from its ring byte
   auto bonus = [&](uint32_t b) -> int32_t {
@@ -368,6 +395,8 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
       upv[0] = shr1_zero(U1[CPL - 1]);
 #pragma unroll
       for (int c = 1; c < CPL; ++c) upv[c] = U1[c - 1];
+      // the top row's U_{d-1}, which the shift drops, for a saved state
+      if constexpr (kSaves && t == G - 1) top_prev = __builtin_amdgcn_readlane(U1[CPL - 1], 63);
       uint64_t imp[CPL];
       uint64_t any = 0;
 #pragma unroll
@@ -467,6 +496,8 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
       upv[0] = shr1_zero(U1[CPL - 1]);
 #pragma unroll
       for (int c = 1; c < CPL; ++c) upv[c] = U1[c - 1];
+      // the top row's U_{d-1}, which the shift drops, for a saved state
+      if constexpr (kSaves && t == G - 1) top_prev = __builtin_amdgcn_readlane(U1[CPL - 1], 63);
       if constexpr (by_masks) {
         cnt = add_lane_bit(cnt, Ld[0] | ((Ld[CPL - 1] | Lm[CPL - 1]) << 1));
 #pragma unroll
@@ -511,6 +542,52 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
     d += G;
   };
 
+  // the state pointer as a wave-uniform value (two 32-bit halves), so that
+  // the branch below and everything set in it stay scalar; the builtin
+  // returns int, so each half goes back to uint32_t before widening (a low
+  // half at or above 2^31 would otherwise sign-extend into the high one)
+  const uint32_t rs_hi =
+      (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)resume >> 32));
+  const uint32_t rs_lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)resume);
+  const uint64_t rs = ((uint64_t)rs_hi << 32) | (uint64_t)rs_lo;
+  if (RESUME && rs) {
+    // continue from a narrower window's state (ResumeHead): its rows land in
+    // the lower part of this window, above them every cell is dead
+    const uint8_t* rsp = (const uint8_t*)rs;
+    const ResumeHead* H = (const ResumeHead*)rsp;
+    d = __builtin_amdgcn_readfirstlane(H->d);
+    base = __builtin_amdgcn_readfirstlane(H->base);
+    thr = __builtin_amdgcn_readfirstlane(H->thr);
+    bi = __builtin_amdgcn_readfirstlane(H->bi);
+    dstar = __builtin_amdgcn_readfirstlane(H->dstar);
+    const int32_t qp = __builtin_amdgcn_readfirstlane(H->q_rows);
+    const int32_t tp = __builtin_amdgcn_readfirstlane(H->top_prev);
+    rebased = H->rebased;
+    // the cells counted before, spread over the lanes' counters
+    const uint64_t c0 = H->cells;
+    cnt = (uint32_t)(c0 >> 6) + ((uint64_t)lane < (c0 & 63) ? 1u : 0u);
+    const int32_t* u1s = (const int32_t*)(rsp + sizeof(ResumeHead));
+    const int32_t* ups = u1s + qp;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int32_t q = irow + c;
+      U1[c] = q < qp ? u1s[q] : 0;
+      Up[c] = q < qp ? ups[q] : q == qp ? tp : 0;
+      const int32_t dm1 = q + 1 < qp ? ups[q + 1] : q + 1 == qp ? tp : 0;  // U_{d-1} of row q
+      Lc[c] = ballot64(U1[c] != 0);
+      Lp[c] = ballot64(dm1 != 0);
+    }
+    // rings: what a run from the seed would hold here, its last RING
+    // positions of b up to the next group's, and the window's rows of a
+    const int32_t fb = ((d + GS - base) | 63) - RING;
+    filled = max(fb, -1);
+    pf_b = word_of(e.wb, e.ob, e.dirb, filled + 1 + lane, n);
+    const int32_t fa = ((base + Q - 1) | 63) - RA;
+    filled_a = max(fa, -1);
+    pf_a = word_of(e.wa, e.oa, e.dir, filled_a + 1 + lane, m);
+    load_a();
+  }
+
   bool overflow = false;
   for (;;) {
     if constexpr (UNIT && CPL == 1) {
@@ -542,6 +619,7 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
           Lc[0] >>= lo;
           Lp[0] >>= lo;
           base += lo;
+          top_prev = 0;  // the rows entering at the top were dead
           load_a();
           continue;
         }
@@ -583,6 +661,7 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
             Lp[k] >>= sl;
           }
           base += sl * CPL;
+          top_prev = 0;  // the rows entering at the top were dead
           load_a();
           continue;
         }
@@ -618,6 +697,30 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
       const int32_t sl = lo / CPL;  // whole lanes below the band
       if (hi - sl * CPL + kShort > Q - 1) {  // cannot fit even a short group
         overflow = true;
+        if constexpr (kSaves) {
+          // the state, into this wave's LDS (the rings are done with)
+          const uint64_t cells = wave_sum_u64(cnt);
+          int32_t* u1s = (int32_t*)ring + sizeof(ResumeHead) / 4;
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) {
+            u1s[irow + c] = U1[c];
+            u1s[Q + irow + c] = Up[c];
+          }
+          if (lane == 0) {
+            ResumeHead H = {};
+            H.d = d;
+            H.base = base;
+            H.thr = thr;
+            H.bi = bi;
+            H.dstar = dstar;
+            H.top_prev = top_prev;
+            H.q_rows = Q;
+            H.rebased = rebased;
+            H.cells = cells;
+            *(ResumeHead*)ring = H;
+          }
+          wave_lds_fence();
+        }
         break;
       }
       if (sl > 0) {
@@ -633,6 +736,7 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
           Lp[c] >>= sl;
         }
         base += sl * CPL;
+        top_prev = 0;  // the rows entering at the top were dead
         hi -= sl * CPL;
         lo -= sl * CPL;
         load_a();

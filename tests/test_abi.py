@@ -154,10 +154,14 @@ def _al(b):
 
 def test_batch_scratch_bytes_layout():
     # per task two 24-byte extension results and six 4-byte lists per
-    # extension, each array rounded up to 256 bytes, plus 3,840 fixed bytes
+    # extension, each array rounded up to 256 bytes, 3,840 fixed bytes, and
+    # the resume states of windows 0..3 (64 << t rows): 2n / (8, 16, 32, 256)
+    # states of 64 + 8 * rows bytes, each pool rounded up to 256 bytes
     lib = _lib.load()
     for n in (0, 1, 2, 5, 31, 32, 33, 1000, 12345, 10**6):
         want = _al(48 * n) + 6 * _al(8 * n) + 3840
+        for t, div in enumerate((8, 16, 32, 256)):
+            want += _al(-(-2 * n // div) * (64 + 8 * (64 << t)))
         assert lib.xd_batch_scratch_bytes(None, n, None) == want, n
     bad = _lib.Tuning(3, 0, 0, 0, 0, 0)  # waves_per_cu must be a multiple of 4
     assert lib.xd_batch_scratch_bytes(ctypes.c_void_p(1), 10, ctypes.byref(bad)) == 0

@@ -329,3 +329,8 @@ def test_wide_windows_parity(form):
     assert_same(got, ref, label="wide " + form)
     if form != "plan":
         assert prof["to_tier3"] > 0 and prof["to_tier4"] > 0, prof
+        # most moves to a wider window resume from the narrower window's
+        # state; past each window's share of state slots they re-run from
+        # the seed (both paths are taken here)
+        moves = sum(prof[f] for f in ("to_tier2", "to_tier3", "to_tier4", "to_tier5"))
+        assert 0 < prof["resumed"] < moves, prof
