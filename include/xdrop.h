@@ -122,7 +122,7 @@ int xd_store_info(const xd_store* store, uint64_t* device_bytes, uint32_t* n_rea
  * hip_stream: a hipStream_t (NULL = the default stream).  The call is
  * asynchronous: it validates the scalar arguments, enqueues kernels and a
  * stream-ordered scratch allocation, and returns.  The scratch size is
- * xd_batch_scratch_bytes(store, n, NULL): about 96 bytes per task plus the
+ * xd_batch_scratch_bytes(store, n, NULL): about 400 bytes per task plus the
  * band tier's rows (xd_tuning.band_blocks; at most 64 MiB by default).
  * k >= 1.  n = 0 is a no-op.
  * Invalid scalars (k, scores, x_scalar when x == NULL) -> XD_EINVAL, nothing
@@ -162,8 +162,11 @@ typedef struct {
   int32_t x_tier1;      /* tasks with X <= x_tier1 start in the 64-cell window (default 32) */
   int32_t x_tier2;      /* X <= x_tier2 start in the 128-cell window (default 80); larger X
                            start in the 256-cell window.  An extension whose band outgrows its
-                           window is re-run in the next wider one (64, 128, 256, 512, 1024),
-                           and past 1024 cells in the band tier (band kept in device memory). */
+                           window moves to the next wider one (64, 128, 256, 512, 1024): out
+                           of the 128-, 256- and 512-cell windows it resumes where it stopped
+                           (while its window's state slots last), out of the 64-cell window
+                           it re-runs from the seed; past 1024 cells the band tier (band kept
+                           in device memory) re-runs it. */
   int32_t band_blocks;  /* workgroups of the band tier, 0..1024; each holds 12 * (longest read
                            of the store + 64) bytes or so of scratch.  0 = as many as fit in
                            64 MiB, at most 16 */
@@ -173,8 +176,11 @@ typedef struct {
  * of n tasks (what the call takes from the library's stream-ordered pool):
  * per task, two 24-byte extension results and six 4-byte-per-extension queue
  * and overflow lists, each array rounded up to 256 bytes, plus 3,840 bytes of
- * counters and tier arguments; with a store, also the band tier's rows for
- * its longest read (tuning->band_blocks workgroups; tuning may be NULL).
+ * counters and tier arguments, plus the resume states of the 128-, 256- and
+ * 512-cell windows: ceil(2n / 16), ceil(2n / 32) and ceil(2n / 256) states
+ * of 64 + 8 * (window rows) bytes, each pool rounded up to 256 bytes (about
+ * 300 bytes per task); with a store, also the band tier's rows for its
+ * longest read (tuning->band_blocks workgroups; tuning may be NULL).
  * store = NULL leaves the rows out.  Host arithmetic only.  0 for an invalid
  * tuning. */
 uint64_t xd_batch_scratch_bytes(const xd_store* store, uint64_t n, const xd_tuning* tuning);

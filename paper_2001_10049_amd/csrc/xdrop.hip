@@ -135,17 +135,19 @@ BandGeom band_geom(uint32_t max_len, uint32_t blocks) {
 
 uint64_t band_bytes(const BandGeom& b) { return (uint64_t)b.blocks * 12ull * (uint64_t)b.cap; }
 
-// Resume states: an extension that overflows window t (64 << t rows, t < 4)
-// into the next one leaves its state (xd::ResumeHead and two int32 rows per
-// window row) in slot s of pool t when its overflow-list slot s is below the
-// pool's capacity, and marks its list entry with kResumeFlag; past that the
-// next window re-runs it from its seed.  Capacities: 2n / kResumeDiv[t]
-// extensions (the share of extensions expected to outgrow window t).
+// Resume states: an extension that overflows window t (64 << t rows; t = 1,
+// 2, 3: the 128-, 256- and 512-cell windows) into the next one leaves its
+// state (xd::ResumeHead and two int32 rows per window row) in slot s of pool
+// t when its overflow-list slot s is below the pool's capacity, and marks its
+// list entry with kResumeFlag; past that the next window re-runs it from its
+// seed, as it re-runs everything that outgrows the 64-cell window (pool 0 is
+// empty).  Capacities: 2n / kResumeDiv[t] extensions, the share expected to
+// outgrow window t.
 constexpr uint32_t kResumeFlag = 0x80000000u;
-constexpr uint32_t kResumeDiv[4] = {8, 16, 32, 256};
+constexpr uint32_t kResumeDiv[4] = {0, 16, 32, 256};
 constexpr uint64_t resume_rec(int t) { return xd::resume_bytes(64 << t); }
 uint32_t resume_cap(uint64_t n, int t) {
-  return (uint32_t)((2 * n + kResumeDiv[t] - 1) / kResumeDiv[t]);
+  return kResumeDiv[t] ? (uint32_t)((2 * n + kResumeDiv[t] - 1) / kResumeDiv[t]) : 0u;
 }
 
 // Device scratch of one batch.
@@ -373,15 +375,12 @@ __global__ __launch_bounds__(256) void k_reset(uint32_t* ctr, uint32_t* hist, Ti
 
 template <int CPL, int GS, bool UNIT>
 __global__ __launch_bounds__(64) void k_ext_first(BatchArgs A, uint32_t e0, uint32_t* ovf_list,
-                                                  uint32_t* ovf_count, uint8_t* state,
-                                                  uint32_t state_cap) {
+                                                  uint32_t* ovf_count) {
   __shared__ uint32_t ring[xd::Tier<CPL, GS>::LDS_WORDS];
   XD_STAMP_T0();
   const uint32_t e = e0 + blockIdx.x;
   // no state: saving one costs this hot kernel about 4 % on c2, where no
   // extension overflows; what outgrows 64 cells re-runs from its seed
-  (void)state;
-  (void)state_cap;
   if (!run_ext<CPL, GS, UNIT, false, false>(A, e, ring, nullptr))
     push_list(ovf_list, ovf_count, e);
   XD_STAMP(stamps::kFirst, 1u);
@@ -1083,8 +1082,8 @@ TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
     TierArgs& T = p.t[t];
     T.in_state = t >= 1 && t <= 4 ? S.state[t - 1] : nullptr;
     T.in_rec = t >= 1 && t <= 4 ? (uint32_t)resume_rec(t - 1) : 0u;
-    T.out_state = t <= 3 ? S.state[t] : nullptr;
-    T.out_cap = t <= 3 ? S.state_cap[t] : 0u;
+    T.out_state = t >= 1 && t <= 3 ? S.state[t] : nullptr;
+    T.out_cap = t >= 1 && t <= 3 ? S.state_cap[t] : 0u;
     T.out_rec = t <= 3 ? (uint32_t)resume_rec(t) : 0u;
     T.pad = 0;
   }
@@ -1120,8 +1119,7 @@ void launch_plain_ext(const BatchArgs& A, const Scratch& S, uint64_t n_ext, hipE
   for (uint64_t e0 = 0; e0 < n_ext; e0 += kChunkBlocks) {
     const uint64_t nb = std::min<uint64_t>(kChunkBlocks, n_ext - e0);
     hipLaunchKernelGGL((k_ext_first<1, 16, UNIT>), dim3((uint32_t)nb), dim3(64), 0, stream, A,
-                       (uint32_t)e0, S.ovf[0], S.ctr + kOvfCount + 0, S.state[0],
-                       S.state_cap[0]);
+                       (uint32_t)e0, S.ovf[0], S.ctr + kOvfCount + 0);
   }
   if (ev) (void)hipEventRecord(ev[1], stream);
   launch_wide<UNIT>(S, kWideBlocks / 4, stream);
