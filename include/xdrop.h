@@ -175,7 +175,7 @@ typedef struct {
 /* Device scratch bytes of one xd_align_batch / xd_align_batch_persistent call
  * of n tasks (what the call takes from the library's stream-ordered pool):
  * per task, two 24-byte extension results and six 4-byte-per-extension queue
- * and overflow lists, each array rounded up to 256 bytes, plus 3,840 bytes of
+ * and overflow lists, each array rounded up to 256 bytes, plus 4,352 bytes of
  * counters and tier arguments, plus the resume states of the 128-, 256- and
  * 512-cell windows: ceil(2n / 16), ceil(2n / 32) and ceil(2n / 256) states
  * of 64 + 8 * (window rows) bytes, each pool rounded up to 256 bytes (about

@@ -169,8 +169,9 @@ constexpr int kHead = 5;       // [5..9] work heads of tiers 0..4
 constexpr int kSeg = 10;       // [10..14] queue start of segments 0..3, then 2n
 constexpr int kBandHead = 15;  // work head of the band tier
 constexpr int kResumed = 16;   // [16..19] moves out of windows 0..3 that carried their state
+constexpr int kSegHead1 = 20;  // work head of the 128-cell window's queue segment (batched form)
 constexpr int kCtrWords = 32;
-constexpr int kTierArgsBytes = 6 * 256;  // >= 6 * sizeof(TierArgs), checked below
+constexpr int kTierArgsBytes = 8 * 256;  // >= sizeof(TierPack), checked below
 constexpr uint64_t kFixedBytes = (kBins * 4 + kCtrWords * 4 + kTierArgsBytes + 255) & ~255ull;
 
 uint64_t state_bytes(uint64_t n, int t) {
@@ -233,7 +234,7 @@ static_assert(xd::kBandedMaxW == XD_BAND_MAX, "band limit");
 static_assert(sizeof(TierArgs) % 4 == 0, "tier arguments copied by words");
 
 struct TierPack {
-  TierArgs t[6];
+  TierArgs t[7];  // [6]: the 128-cell window's queue segment alone (batched form)
   xd::pair::Shared pz;  // scalars of the packed 64-cell tier
 };
 static_assert(sizeof(TierPack) <= kTierArgsBytes, "tier argument area");
@@ -392,7 +393,9 @@ __global__ __launch_bounds__(64) void k_ext_first(BatchArgs A, uint32_t e0, uint
 // in_count extensions that overflowed the previous tier.  Overflowing
 // extensions go to out_list, or are marked unresolved when there is no
 // wider tier.
-template <int CPL, int GS, bool UNIT, int WAVES>
+// SAVE: leave the state of what overflows (for the next window to resume);
+// RESUME: take such states from in_list.
+template <int CPL, int GS, bool UNIT, int WAVES, bool SAVE, bool RESUME>
 __global__ __launch_bounds__(64 * WAVES) void k_ext_tier(const TierArgs* __restrict__ P) {
   static_assert(WAVES * xd::Tier<CPL, GS>::LDS_WORDS * 4 <= 64 * 1024, "LDS per block");
   __shared__ uint32_t rings[WAVES][xd::Tier<CPL, GS>::LDS_WORDS];
@@ -423,9 +426,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_ext_tier(const TierArgs* __restr
 #ifdef XD_WAVE_STAMPS
     ++taken;
 #endif
-    // the 64-cell windows neither leave nor take states (the 128-cell window
-    // receives none), the widest leaves none (the band tier re-runs it)
-    if (!run_ext<CPL, GS, UNIT, (CPL >= 2 && CPL < 16), (CPL >= 4)>(Q.A, e, rings[w], resume)) {
+    if (!run_ext<CPL, GS, UNIT, SAVE, RESUME>(Q.A, e, rings[w], resume)) {
       const TierArgs& R = *pp;
       overflow_to(R.A.ext, R.out_list, R.out_count, R.out_state, R.out_cap, R.out_rec, e,
                   rings[w]);
@@ -1067,8 +1068,14 @@ TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
   TierPack p;
   p.t[0] = {A, S.queue, c + kSeg + 0, nullptr, nullptr, c + kHead + 0, S.ovf[0],
             c + kOvfCount + 0};
-  p.t[1] = {A, S.queue, segs ? c + kSeg + 1 : nullptr, S.ovf[0], c + kOvfCount + 0,
-            c + kHead + 1, S.ovf[1], c + kOvfCount + 1};
+  // the 128-cell window's list (what outgrew 64 cells, resumable onwards)
+  // and its queue segment (batched form: X in (x_tier1, x_tier2], started
+  // here; they leave no state, so that the kernel that runs them keeps the
+  // register budget of one without saving) run as two launches
+  p.t[1] = {A, S.queue, nullptr, S.ovf[0], c + kOvfCount + 0, c + kHead + 1, S.ovf[1],
+            c + kOvfCount + 1};
+  p.t[6] = {A, S.queue, segs ? c + kSeg + 1 : nullptr, nullptr, nullptr, c + kSegHead1,
+            S.ovf[1], c + kOvfCount + 1};
   p.t[2] = {A, S.queue, segs ? c + kSeg + 2 : nullptr, S.ovf[1], c + kOvfCount + 1,
             c + kHead + 2, S.ovf[2], c + kOvfCount + 2};
   p.t[3] = {A, S.queue, nullptr, S.ovf[2], c + kOvfCount + 2, c + kHead + 3, S.ovf[3],
@@ -1078,7 +1085,7 @@ TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
   p.t[5] = {A, S.queue, nullptr, S.ovf[4], c + kOvfCount + 4, c + kBandHead, nullptr, nullptr};
   // resume states: window t leaves them in pool t, window t + 1 reads them;
   // the band tier re-runs what outgrows the 1024-cell window
-  for (int t = 0; t < 6; ++t) {
+  for (int t = 0; t < 7; ++t) {
     TierArgs& T = p.t[t];
     T.in_state = t >= 1 && t <= 4 ? S.state[t - 1] : nullptr;
     T.in_rec = t >= 1 && t <= 4 ? (uint32_t)resume_rec(t - 1) : 0u;
@@ -1087,19 +1094,31 @@ TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
     T.out_rec = t <= 3 ? (uint32_t)resume_rec(t) : 0u;
     T.pad = 0;
   }
+  p.t[6].in_state = nullptr;
+  p.t[6].in_rec = 0u;
+  p.t[6].out_state = nullptr;
+  p.t[6].out_cap = 0u;
   p.pz = pair_shared(A.sc);
   return p;
 }
 
+// The wider windows: 128 (its queue segment, then its list), 256, 512, 1024
+// cells, then the band tier.  Saving and resuming: 128 saves, 256 and 512
+// resume and save, 1024 resumes.
 template <bool UNIT>
-void launch_wide(const Scratch& S, uint32_t blocks, hipStream_t stream) {
+void launch_wide(const Scratch& S, uint32_t blocks, hipStream_t stream, bool segs) {
   const TierArgs* ta = (const TierArgs*)S.targs;
-  hipLaunchKernelGGL((k_ext_tier<2, 8, UNIT, 4>), dim3(blocks), dim3(256), 0, stream, ta + 1);
-  hipLaunchKernelGGL((k_ext_tier<4, 4, UNIT, 4>), dim3(blocks), dim3(256), 0, stream, ta + 2);
-  hipLaunchKernelGGL((k_ext_tier<8, 4, UNIT, 2>), dim3(2 * blocks), dim3(128), 0, stream,
-                     ta + 3);
-  hipLaunchKernelGGL((k_ext_tier<16, 2, UNIT, 1>), dim3(4 * blocks), dim3(64), 0, stream,
-                     ta + 4);
+  if (segs)
+    hipLaunchKernelGGL((k_ext_tier<2, 8, UNIT, 4, false, false>), dim3(blocks), dim3(256), 0,
+                       stream, ta + 6);
+  hipLaunchKernelGGL((k_ext_tier<2, 8, UNIT, 4, true, false>), dim3(blocks), dim3(256), 0,
+                     stream, ta + 1);
+  hipLaunchKernelGGL((k_ext_tier<4, 4, UNIT, 4, true, true>), dim3(blocks), dim3(256), 0,
+                     stream, ta + 2);
+  hipLaunchKernelGGL((k_ext_tier<8, 4, UNIT, 2, true, true>), dim3(2 * blocks), dim3(128), 0,
+                     stream, ta + 3);
+  hipLaunchKernelGGL((k_ext_tier<16, 2, UNIT, 1, false, true>), dim3(4 * blocks), dim3(64), 0,
+                     stream, ta + 4);
   hipLaunchKernelGGL(k_ext_band, dim3(S.geom.blocks), dim3(64 * kBandWaves), 0, stream, ta + 5,
                      S.band, S.geom.cap);
 }
@@ -1122,13 +1141,14 @@ void launch_plain_ext(const BatchArgs& A, const Scratch& S, uint64_t n_ext, hipE
                        (uint32_t)e0, S.ovf[0], S.ctr + kOvfCount + 0);
   }
   if (ev) (void)hipEventRecord(ev[1], stream);
-  launch_wide<UNIT>(S, kWideBlocks / 4, stream);
+  launch_wide<UNIT>(S, kWideBlocks / 4, stream, false);
   if (ev) (void)hipEventRecord(ev[2], stream);
 }
 
 template <bool UNIT, int GS>
 void launch_tier0(const Scratch& S, uint32_t blocks, hipStream_t stream) {
-  hipLaunchKernelGGL((k_ext_tier<1, GS, UNIT, 4>), dim3(blocks), dim3(256), 0, stream,
+  hipLaunchKernelGGL((k_ext_tier<1, GS, UNIT, 4, false, false>), dim3(blocks), dim3(256), 0,
+                     stream,
                      (const TierArgs*)S.targs);
 }
 
@@ -1154,7 +1174,7 @@ void launch_persistent_ext(const BatchArgs& A, const Scratch& S, uint64_t n_ext,
   else
     launch_tier0<UNIT, 8>(S, blocks, stream);
   if (ev) (void)hipEventRecord(ev[1], stream);
-  launch_wide<UNIT>(S, blocks, stream);
+  launch_wide<UNIT>(S, blocks, stream, true);
   if (ev) (void)hipEventRecord(ev[2], stream);
 }
 
