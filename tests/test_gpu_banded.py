@@ -81,3 +81,22 @@ def test_banded_scoring(scheme):
     w = synth.config("c1-small")
     got, ref = run(w, np.full(w.n_tasks, 20, np.int32), scheme)
     assert_same(got, ref, "scheme %s" % (scheme,))
+
+
+def test_banded_scalar_band_width():
+    # the scalar w_scalar form (no per-task array), with an odd task count
+    w = synth.config("c2-small")
+    w = w.subset(np.arange(w.n_tasks - (1 - w.n_tasks % 2)))
+    store = xd.ReadStore.from_workload(w)
+    try:
+        pairs, seeds, _ = xd.workload_tensors(w, "cuda")
+        for wdt in (0, 16, 21):
+            out = xd.banded_batch(store, pairs, seeds, w=None, w_scalar=wdt, k=w.k)
+            torch.cuda.synchronize()
+            got = {k: v.cpu().numpy() for k, v in out.items()}
+            ref = oracle.banded_batch(w.codes, w.off, w.length, np.stack([w.ra, w.rb], 1),
+                                      np.stack([w.pa, w.pb], 1),
+                                      np.full(w.n_tasks, wdt, np.int32), k=w.k)
+            assert_same(got, ref, "scalar w=%d" % wdt)
+    finally:
+        store.close()
