@@ -70,10 +70,13 @@ __device__ unsigned long long g_pair_events[16];
 constexpr int GS = 16;      // antidiagonals per group
 constexpr int HG = 8;       // steps whose improvement masks are kept at once
 constexpr int kShort = 4;   // group length near the window top
-constexpr int RING = 256;   // b ring words (one per j)
+// b ring words (one per j): the window's 64 rows, a re-centring jump of up
+// to 64 rows, the group, and two refill chunks (the one a refill needs and
+// the next, written in the same refill)
+constexpr int RING = 512;
 constexpr int MASK = RING - 1;
 constexpr int MIR = 1 + GS; // mirrored words after the ring
-constexpr int RA = 128;     // a ring bytes (one per i)
+constexpr int RA = 256;     // a ring bytes (one per i): 64 rows + two chunks
 constexpr int SLOT_WORDS = RING + MIR + RA / 4;
 constexpr int LDS_WORDS = 2 * SLOT_WORDS;
 constexpr int32_t kBase = 1024;
@@ -144,13 +147,18 @@ enum {
 // blocks, never by compiled code.
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// leading zeros of a lane mask, -1 for an empty one; trailing zeros
-// (compiled code on the uniform mask: scalar instructions)
+// leading and trailing zeros of a uniform lane mask, -1 for an empty one
+// (what the scalar bit scans return for zero, which compiled code would
+// test and select on its own)
 __device__ __forceinline__ int32_t mask_clz(uint64_t M) {
-  return M ? (int32_t)__builtin_clzll(M) : -1;
+  int32_t r;
+  asm("s_flbit_i32_b64 %0, %1" : "=s"(r) : "s"(M));
+  return r;
 }
 __device__ __forceinline__ int32_t mask_ctz(uint64_t M) {
-  return M ? (int32_t)__builtin_ctzll(M) : 64;
+  int32_t r;
+  asm("s_ff1_i32_b64 %0, %1" : "=s"(r) : "s"(M));
+  return r;
 }
 
 template <bool MASKED>
@@ -290,7 +298,7 @@ __device__ __forceinline__ uint32_t code_in(uint32_t w, int32_t o, int32_t dr, i
   return (w >> (((o + dr * (q - 1)) & 15) << 1)) & 3u;
 }
 
-// b ring of slot H up to j = jhi: word j holds, in byte c, the diagonal
+// b ring of slot H up to at least j = jhi: word j holds, in byte c, the diagonal
 // bonus of a row whose a-code is c against b_j: mismatch + 2g, plus 1 -
 // mismatch when c = code(b_j); 0 outside 1..n.  Refilled 64 j at a time from
 // the prefetched word, the next chunk's word loaded meanwhile.
@@ -316,8 +324,9 @@ __device__ __forceinline__ void fill_b(Slot& S, const Shared* Zp, uint32_t* lds,
   wave_lds_fence();
 }
 
-// a ring of slot H up to row base + 63, and each lane's a-code byte offset
-// added to its ring's LDS byte address
+// a ring of slot H holding row base + 63 (a refill writes the chunk after
+// too), and each lane's a-code byte offset added to its ring's LDS byte
+// address
 template <int H>
 __device__ __forceinline__ void load_a(Slot& S, uint32_t* lds) {
   uint32_t* ring = slot_ring<H>(lds);
@@ -329,7 +338,7 @@ __device__ __forceinline__ void load_a(Slot& S, uint32_t* lds) {
     const uint32_t* wa = cold_ptr(cold, kCwaLo);
     const int32_t oa = (int32_t)cold_get(cold, kCoa), dir = (int32_t)cold_get(cold, kCdir);
     XD_PAIR_EVENT(9);
-    while (filled_a < S.base + 63) {
+    while (filled_a < S.base + 127) {
       const int32_t i = filled_a + 1 + lane;
       aring[i & (RA - 1)] = (uint8_t)((i >= 1 & i <= S.m) ? code_in(S.pf_a, oa, dir, i) : 0u);
       S.pf_a = word_of(wa, oa, dir, i + 64, S.m);
@@ -460,7 +469,7 @@ __device__ __forceinline__ int prepare(Slot& S, const Shared* Zp, uint32_t* lds,
     const int32_t G = full ? GS : kShort;
     const int32_t dv = S.d - S.base;
     if (S.filled < dv + G) {
-      fill_b<H>(S, Zp, lds, S.d + GS - S.base);
+      fill_b<H>(S, Zp, lds, S.d + GS - S.base + 64);
       continue;
     }
     const int32_t room_a = S.m - S.base - hi, room_b = S.base + lo - S.d + S.n;
@@ -626,6 +635,37 @@ __device__ __forceinline__ int32_t fast_test(uint64_t M, const FastOps& f, int32
   return (z - GS) | (z + f.mb) | (lo + f.nb) | f.fb;
 }
 
+// Makes a slot that failed the fast test pass it, if only its window top
+// or its ring stood in the way: slides the window up to the band's lowest
+// live row when the band nears the top (and a full group then fits), and
+// refills the ring one chunk past the group.  Keeps z, lo and f in step with
+// the slot.  False: the slot needs the general path (a wall within reach,
+// an end, a band too wide for a full group).
+template <int H>
+__device__ __forceinline__ bool fix(Slot& S, const Shared* Zp, uint32_t* lds, uint32_t& U1,
+                                    uint32_t& Up, int32_t z, int32_t lo, FastOps& f) {
+  if (!S.active) return false;
+  if (z < GS) {
+    if (z < 0 || lo <= 0 || z + lo < GS) return false;
+    recenter<H>(S, lds, lo, U1, Up);
+    XD_PAIR_EVENT(4);
+    // the slide leaves room_a and room_b as they were and moves the ring
+    // margin with the window
+    z += lo;
+    f.mb -= lo;
+    f.nb += lo;
+    f.fb += lo;
+    lo = 0;
+  }
+  if (((z + f.mb) | (lo + f.nb)) < 0) return false;
+  if (f.fb < 0) {
+    fill_b<H>(S, Zp, lds, S.d + GS - S.base + 64);
+    XD_PAIR_EVENT(5);
+    f.fb = S.filled - (S.d - S.base) - GS;
+  }
+  return true;
+}
+
 // Runs extensions two at a time until W runs out.  W supplies them
 // (W.next(e, ex) -> false when none is left) and takes the outcome
 // (W.done(e, result), W.overflow(e) when the band outgrew the window).
@@ -735,40 +775,14 @@ __device__ void run(Work& W, uint32_t* lds, const Shared* Zp) {
       int32_t ta = fast_test(A.M, fa, za, la);
       int32_t tb = fast_test(B.M, fb, zb, lb);
       if ((ta | tb) < 0) {
-        // slide a window up when its band nears the top (and fits), refill
-        // a ring that runs short; anything else goes to the general path
-        bool again = false;
-        if (ta < 0 && A.active) {
-          if (za >= 0 && za < GS && la > 0 && 63 - za - la + kShort <= 63) {
-            recenter<0>(A, lds, la, U1, Up);
-            XD_PAIR_EVENT(4);
-            again = true;
-          } else if (fa.fb < 0 && (za - GS | za + fa.mb | la + fa.nb) >= 0) {
-            fill_b<0>(A, Zp, lds, A.d + GS - A.base);
-            XD_PAIR_EVENT(5);
-            again = true;
-          }
-        }
-        if (tb < 0 && B.active) {
-          if (zb >= 0 && zb < GS && lb > 0 && 63 - zb - lb + kShort <= 63) {
-            recenter<1>(B, lds, lb, U1, Up);
-            XD_PAIR_EVENT(4);
-            again = true;
-          } else if (fb.fb < 0 && (zb - GS | zb + fb.mb | lb + fb.nb) >= 0) {
-            fill_b<1>(B, Zp, lds, B.d + GS - B.base);
-            XD_PAIR_EVENT(5);
-            again = true;
-          }
-        }
-        if (!again) {
+        // slide a window up when its band nears the top, refill a ring that
+        // runs short, on the spot; anything else goes to the general path
+        if ((ta < 0 && !fix<0>(A, Zp, lds, U1, Up, za, la, fa)) ||
+            (tb < 0 && !fix<1>(B, Zp, lds, U1, Up, zb, lb, fb))) {
           XD_PAIR_EVENT(7);
           break;
         }
         upv = shr1(U1);
-        fa = fast_ops(A);
-        fb = fast_ops(B);
-        ++left;  // an event is not a group
-        continue;
       }
       if constexpr (Work::kTrace) W.trace(kGo, A, B, U1, Up, upv, NT, TP, KX);
       group<false, GS>(A, B, U1, Up, upv, cnt, NT, TP, KX, G1, GB1, ONE);
