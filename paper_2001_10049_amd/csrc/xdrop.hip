@@ -395,8 +395,12 @@ __global__ __launch_bounds__(64) void k_ext_first(BatchArgs A, uint32_t e0, uint
 // wider tier.
 // SAVE: leave the state of what overflows (for the next window to resume);
 // RESUME: take such states from in_list.
+// (the 128-cell window's queue segment, which saves nothing, is held to 80
+// VGPRs: 6 waves per SIMD)
 template <int CPL, int GS, bool UNIT, int WAVES, bool SAVE, bool RESUME>
-__global__ __launch_bounds__(64 * WAVES) void k_ext_tier(const TierArgs* __restrict__ P) {
+__global__ __launch_bounds__(64 * WAVES)
+__attribute__((amdgpu_waves_per_eu(CPL == 2 && !SAVE ? 6 : 1)))
+void k_ext_tier(const TierArgs* __restrict__ P) {
   static_assert(WAVES * xd::Tier<CPL, GS>::LDS_WORDS * 4 <= 64 * 1024, "LDS per block");
   __shared__ uint32_t rings[WAVES][xd::Tier<CPL, GS>::LDS_WORDS];
   const int w = threadIdx.x >> 6;

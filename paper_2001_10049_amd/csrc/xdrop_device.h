@@ -84,17 +84,18 @@ template <int CPL, int GS>
 struct Tier {
   static constexpr int Q = 64 * CPL;         // window rows
   // b ring (one word per j): holds every j the window can need between
-  // refills, including after a re-centring jump of up to Q rows
-  static constexpr int kNeed = 2 * Q + 64 + GS + 2;
+  // refills, including after a re-centring jump of up to Q rows; a refill
+  // writes the chunk that is needed and the one after it
+  static constexpr int kNeed = 2 * Q + 128 + GS + 2;
   static constexpr int RING = kNeed <= 256 ? 256
                               : kNeed <= 512 ? 512
                               : kNeed <= 1024 ? 1024
                               : kNeed <= 2048 ? 2048 : 4096;
   static constexpr int MIR = CPL + GS;       // mirrored words after the ring
-  // a ring (one byte per i): the window's rows plus one refill chunk
-  static constexpr int RA = Q + 64 <= 128 ? 128
-                            : Q + 64 <= 256 ? 256
-                            : Q + 64 <= 512 ? 512 : 2048;
+  // a ring (one byte per i): the window's rows plus two refill chunks
+  static constexpr int RA = Q + 128 <= 256 ? 256
+                            : Q + 128 <= 512 ? 512
+                            : Q + 128 <= 1024 ? 1024 : 2048;
   static constexpr int LDS_WORDS = RING + MIR + RA / 4;
 };
 
@@ -303,7 +304,10 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
   // b ring: chunk c holds j in [64c, 64c+63]; pf_b carries the next chunk
   int32_t filled = -1;  // highest j whose ring slot holds b_j
   uint32_t pf_b = word_of(e.wb, e.ob, e.dirb, lane, n);
+  // when the ring lacks j = jhi: fills it to jhi plus one chunk (every
+  // other refill is then skipped)
   auto fill_to = [&](int32_t jhi) {
+    if (filled < jhi) jhi += 64;
     while (filled < jhi) {
       const int32_t j = filled + 1 + lane;
       const uint32_t sh = 8u * (code_in(pf_b, e.ob, e.dirb, j) ^ e.comp);
@@ -321,6 +325,7 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
   int32_t filled_a = -1;
   uint32_t pf_a = word_of(e.wa, e.oa, e.dir, lane, m);
   auto fill_a_to = [&](int32_t ihi) {
+    if (filled_a < ihi) ihi += 64;
     while (filled_a < ihi) {
       const int32_t i = filled_a + 1 + lane;
       aring[i & (RA - 1)] = (uint8_t)((i >= 1 & i <= m) ? code_in(pf_a, e.oa, e.dir, i) : 0u);
@@ -577,12 +582,13 @@ __device__ __forceinline__ bool extend(const Ext& e, const Scoring& sc,
       Lc[c] = ballot64(U1[c] != 0);
       Lp[c] = ballot64(dm1 != 0);
     }
-    // rings: what a run from the seed would hold here, its last RING
-    // positions of b up to the next group's, and the window's rows of a
-    const int32_t fb = ((d + GS - base) | 63) - RING;
+    // rings: the last RING positions of b up to one chunk past the next
+    // group's, and the window's rows of a (the next refill of each fills
+    // the whole ring)
+    const int32_t fb = ((d + GS - base) | 63) + 64 - RING;
     filled = max(fb, -1);
     pf_b = word_of(e.wb, e.ob, e.dirb, filled + 1 + lane, n);
-    const int32_t fa = ((base + Q - 1) | 63) - RA;
+    const int32_t fa = ((base + Q - 1) | 63) + 64 - RA;
     filled_a = max(fa, -1);
     pf_a = word_of(e.wa, e.oa, e.dir, filled_a + 1 + lane, m);
     load_a();
