@@ -122,7 +122,7 @@ int xd_store_info(const xd_store* store, uint64_t* device_bytes, uint32_t* n_rea
  * hip_stream: a hipStream_t (NULL = the default stream).  The call is
  * asynchronous: it validates the scalar arguments, enqueues kernels and a
  * stream-ordered scratch allocation, and returns.  The scratch size is
- * xd_batch_scratch_bytes(store, n, NULL): about 400 bytes per task plus the
+ * xd_batch_scratch_bytes(store, n, NULL): about 540 bytes per task plus the
  * band tier's rows (xd_tuning.band_blocks; at most 64 MiB by default).
  * k >= 1.  n = 0 is a no-op.
  * Invalid scalars (k, scores, x_scalar when x == NULL) -> XD_EINVAL, nothing
@@ -176,10 +176,11 @@ typedef struct {
  * of n tasks (what the call takes from the library's stream-ordered pool):
  * per task, two 24-byte extension results and six 4-byte-per-extension queue
  * and overflow lists, each array rounded up to 256 bytes, plus 4,352 bytes of
- * counters and tier arguments, plus the resume states of the 128-, 256- and
- * 512-cell windows: ceil(2n / 16), ceil(2n / 32) and ceil(2n / 256) states
- * of 64 + 8 * (window rows) bytes, each pool rounded up to 256 bytes (about
- * 300 bytes per task); with a store, also the band tier's rows for its
+ * counters and tier arguments, plus the resume states of the 64- (batched
+ * form), 128-, 256- and 512-cell windows: ceil(2n / 8), ceil(2n / 16),
+ * ceil(2n / 32) and ceil(2n / 256) states of 64 + 8 * (window rows) bytes,
+ * each pool rounded up to 256 bytes (about 445 bytes per task); with a
+ * store, also the band tier's rows for its
  * longest read (tuning->band_blocks workgroups; tuning may be NULL).
  * store = NULL leaves the rows out.  Host arithmetic only.  0 for an invalid
  * tuning. */

@@ -288,10 +288,13 @@ __device__ __forceinline__ const uint32_t* cold_ptr(const uint32_t* c, int k) {
 }
 
 // packed word holding character q (1-based) of a or b, or 0 outside [1, lim]
+// (a global load: the read pointers come back from LDS as generic ones, and
+// a flat load would also hold up the next wait for LDS results)
+typedef __attribute__((address_space(1))) const uint32_t glob_u32;
 __device__ __forceinline__ uint32_t word_of(const uint32_t* w, int32_t o, int32_t dr, int32_t q,
                                             int32_t lim) {
   uint32_t v = 0;
-  if (q >= 1 & q <= lim) v = w[(o + dr * (q - 1)) >> 4];
+  if (q >= 1 & q <= lim) v = ((glob_u32*)w)[(o + dr * (q - 1)) >> 4];
   return v;
 }
 __device__ __forceinline__ uint32_t code_in(uint32_t w, int32_t o, int32_t dr, int32_t q) {
@@ -426,6 +429,41 @@ __device__ __forceinline__ ExtOut result(const Slot& S, const Shared* Zp, const 
   return o;
 }
 
+// Slot H's state where its band outgrew the window, as a ResumeHead and
+// two rows of 64 int32 at the start of its ring (the ring is done with),
+// in the 32-bit tiers' units: U = S + g*d + X + kBias0 is v + R + 7168 for
+// a live value v of this tier (v = S + g*d + X + 1024 - R), 0 for a dead
+// cell; the threshold converts the same way.  Taken at a group boundary,
+// where the top row of the antidiagonal before the last is dead (the band
+// stays below it through a group), so top_prev is 0.
+template <int H>
+__device__ __forceinline__ const uint32_t* save(const Slot& S, uint32_t* lds, uint32_t U1,
+                                                uint32_t Up, uint32_t cnt, uint32_t NT) {
+  const int lane = lane_id();
+  uint32_t* ring = slot_ring<H>(lds);
+  const uint32_t off = cold_get(slot_cold<H>(lds), kCR) + 7168u - kPat;
+  const uint64_t cells = wave_sum_u64v((uint64_t)S.cnt32 + count_half<H>(cnt));
+  const uint32_t u1 = (uint32_t)half_of<H>(U1), up = (uint32_t)half_of<H>(Up);
+  int32_t* rows = (int32_t*)(ring + sizeof(ResumeHead) / 4);
+  rows[lane] = u1 ? (int32_t)(u1 + off) : 0;
+  rows[64 + lane] = up ? (int32_t)(up + off) : 0;
+  if (lane == 0) {
+    ResumeHead h = {};
+    h.d = S.d;
+    h.base = S.base;
+    h.thr = half_of<H>(NT) - (int32_t)kNegPat + 1 + (int32_t)(off + kPat);
+    h.bi = S.bi;
+    h.dstar = S.dstar;
+    h.top_prev = 0;
+    h.q_rows = 64;
+    h.rebased = 0;
+    h.cells = cells;
+    *(ResumeHead*)ring = h;
+  }
+  wave_lds_fence();
+  return ring;
+}
+
 // Slides slot H's window up by sl whole lanes.
 template <int H>
 __device__ __forceinline__ void recenter(Slot& S, uint32_t* lds, int32_t sl, uint32_t& U1,
@@ -547,8 +585,9 @@ __device__ __forceinline__ void group(Slot& A, Slot& B, uint32_t& U1, uint32_t& 
                                       uint32_t KX, uint32_t G1, uint32_t GB1, uint32_t ONE) {
   const int32_t lane = lane_id();
   // bonus byte addresses of both slots at the group's first antidiagonal
-  const uint32_t ra = (uint32_t)(A.d + 1 - A.base - lane) & MASK;
-  const uint32_t rb = (uint32_t)(B.d + 1 - B.base - lane) & MASK;
+  // (the scalar part first: one vector subtract per slot)
+  const uint32_t ra = (uni((uint32_t)(A.d + 1 - A.base)) - (uint32_t)lane) & MASK;
+  const uint32_t rb = (uni((uint32_t)(B.d + 1 - B.base)) - (uint32_t)lane) & MASK;
   const lds_u8* a0 = (const lds_u8*)(uintptr_t)(A.aad + (ra << 2));
   const lds_u8* a1 = (const lds_u8*)(uintptr_t)(B.aad + (rb << 2));
   constexpr int K = G < HG ? G : HG;
@@ -668,7 +707,8 @@ __device__ __forceinline__ bool fix(Slot& S, const Shared* Zp, uint32_t* lds, ui
 
 // Runs extensions two at a time until W runs out.  W supplies them
 // (W.next(e, ex) -> false when none is left) and takes the outcome
-// (W.done(e, result), W.overflow(e) when the band outgrew the window).
+// (W.done(e, result), W.overflow(e, state) when the band outgrew the window,
+// with its state in LDS as save() leaves it).
 //
 // The group loop first tries the common case for both slots at once (the
 // fast test above, idle slots always passing); a slot that fails it usually
@@ -723,9 +763,11 @@ __device__ void run(Work& W, uint32_t* lds, const Shared* Zp) {
     int sb = B.active ? prepare<1>(B, Zp, lds, U1, Up, moved) : kGo;
     if ((sa | sb) & (kEnd | kOvf)) {
       if (sa & kEnd) W.done(cold_get(slot_cold<0>(lds), kCe), result<0>(A, Zp, lds, cnt, NT));
-      if (sa & kOvf) W.overflow(cold_get(slot_cold<0>(lds), kCe));
+      if (sa & kOvf)
+        W.overflow(cold_get(slot_cold<0>(lds), kCe), save<0>(A, lds, U1, Up, cnt, NT));
       if (sb & kEnd) W.done(cold_get(slot_cold<1>(lds), kCe), result<1>(B, Zp, lds, cnt, NT));
-      if (sb & kOvf) W.overflow(cold_get(slot_cold<1>(lds), kCe));
+      if (sb & kOvf)
+        W.overflow(cold_get(slot_cold<1>(lds), kCe), save<1>(B, lds, U1, Up, cnt, NT));
       if (sa & (kEnd | kOvf)) {
         A.active = 0;
         A.M = 1;

@@ -135,16 +135,17 @@ BandGeom band_geom(uint32_t max_len, uint32_t blocks) {
 
 uint64_t band_bytes(const BandGeom& b) { return (uint64_t)b.blocks * 12ull * (uint64_t)b.cap; }
 
-// Resume states: an extension that overflows window t (64 << t rows; t = 1,
-// 2, 3: the 128-, 256- and 512-cell windows) into the next one leaves its
-// state (xd::ResumeHead and two int32 rows per window row) in slot s of pool
-// t when its overflow-list slot s is below the pool's capacity, and marks its
-// list entry with kResumeFlag; past that the next window re-runs it from its
-// seed, as it re-runs everything that outgrows the 64-cell window (pool 0 is
-// empty).  Capacities: 2n / kResumeDiv[t] extensions, the share expected to
-// outgrow window t.
+// Resume states: an extension that overflows window t (64 << t rows; t = 0:
+// the batched form's packed 64-cell tier, t = 1, 2, 3: the 128-, 256- and
+// 512-cell windows) into the next one leaves its state (xd::ResumeHead and
+// two int32 rows per window row) in slot s of pool t when its overflow-list
+// slot s is below the pool's capacity, and marks its list entry with
+// kResumeFlag; past that the next window re-runs it from its seed, as it
+// re-runs what outgrows the plain form's 64-cell kernel (which saves
+// nothing).  Capacities: 2n / kResumeDiv[t] extensions, the share expected
+// to outgrow window t.
 constexpr uint32_t kResumeFlag = 0x80000000u;
-constexpr uint32_t kResumeDiv[4] = {0, 16, 32, 256};
+constexpr uint32_t kResumeDiv[4] = {8, 16, 32, 256};
 constexpr uint64_t resume_rec(int t) { return xd::resume_bytes(64 << t); }
 uint32_t resume_cap(uint64_t n, int t) {
   return kResumeDiv[t] ? (uint32_t)((2 * n + kResumeDiv[t] - 1) / kResumeDiv[t]) : 0u;
@@ -396,10 +397,10 @@ __global__ __launch_bounds__(64) void k_ext_first(BatchArgs A, uint32_t e0, uint
 // SAVE: leave the state of what overflows (for the next window to resume);
 // RESUME: take such states from in_list.
 // (the 128-cell window's queue segment, which saves nothing, is held to 80
-// VGPRs: 6 waves per SIMD)
+// VGPRs, 6 waves per SIMD; its list, which resumes and saves, to 96, 5 waves)
 template <int CPL, int GS, bool UNIT, int WAVES, bool SAVE, bool RESUME>
 __global__ __launch_bounds__(64 * WAVES)
-__attribute__((amdgpu_waves_per_eu(CPL == 2 && !SAVE ? 6 : 1)))
+__attribute__((amdgpu_waves_per_eu(CPL == 2 ? (SAVE ? 5 : 6) : 1)))
 void k_ext_tier(const TierArgs* __restrict__ P) {
   static_assert(WAVES * xd::Tier<CPL, GS>::LDS_WORDS * 4 <= 64 * 1024, "LDS per block");
   __shared__ uint32_t rings[WAVES][xd::Tier<CPL, GS>::LDS_WORDS];
@@ -451,6 +452,7 @@ struct PairWork {
   template <class... T>
   __device__ void trace(T&&...) {}
 
+  // an extension never started here (X above the packed limit)
   __device__ void overflow(uint32_t e) {
     const TierArgs& R = *pp;
     if (R.out_list) {
@@ -459,6 +461,11 @@ struct PairWork {
       ExtOut o = {0, 0, 0, xd::kExtOverflow, 0};
       R.A.ext[e] = o;
     }
+  }
+  // one whose band outgrew the window, its state at state (LDS)
+  __device__ void overflow(uint32_t e, const uint32_t* state) {
+    const TierArgs& R = *pp;
+    overflow_to(R.A.ext, R.out_list, R.out_count, R.out_state, R.out_cap, R.out_rec, e, state);
   }
   __device__ void done(uint32_t e, const ExtOut& o) {
     if (xd::lane_id() == 0) pp->A.ext[e] = o;
@@ -1093,8 +1100,8 @@ TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
     TierArgs& T = p.t[t];
     T.in_state = t >= 1 && t <= 4 ? S.state[t - 1] : nullptr;
     T.in_rec = t >= 1 && t <= 4 ? (uint32_t)resume_rec(t - 1) : 0u;
-    T.out_state = t >= 1 && t <= 3 ? S.state[t] : nullptr;
-    T.out_cap = t >= 1 && t <= 3 ? S.state_cap[t] : 0u;
+    T.out_state = t <= 3 ? S.state[t] : nullptr;
+    T.out_cap = t <= 3 ? S.state_cap[t] : 0u;
     T.out_rec = t <= 3 ? (uint32_t)resume_rec(t) : 0u;
     T.pad = 0;
   }
@@ -1107,15 +1114,17 @@ TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
 }
 
 // The wider windows: 128 (its queue segment, then its list), 256, 512, 1024
-// cells, then the band tier.  Saving and resuming: 128 saves, 256 and 512
-// resume and save, 1024 resumes.
+// cells, then the band tier.  Saving and resuming: the 128-cell list
+// resumes what the packed 64-cell tier saved, and saves; 256 and 512 resume
+// and save, 1024 resumes; the 128-cell queue segment starts its extensions
+// and saves nothing.
 template <bool UNIT>
 void launch_wide(const Scratch& S, uint32_t blocks, hipStream_t stream, bool segs) {
   const TierArgs* ta = (const TierArgs*)S.targs;
   if (segs)
     hipLaunchKernelGGL((k_ext_tier<2, 8, UNIT, 4, false, false>), dim3(blocks), dim3(256), 0,
                        stream, ta + 6);
-  hipLaunchKernelGGL((k_ext_tier<2, 8, UNIT, 4, true, false>), dim3(blocks), dim3(256), 0,
+  hipLaunchKernelGGL((k_ext_tier<2, 8, UNIT, 4, true, true>), dim3(blocks), dim3(256), 0,
                      stream, ta + 1);
   hipLaunchKernelGGL((k_ext_tier<4, 4, UNIT, 4, true, true>), dim3(blocks), dim3(256), 0,
                      stream, ta + 2);

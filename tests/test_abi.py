@@ -155,13 +155,13 @@ def _al(b):
 def test_batch_scratch_bytes_layout():
     # per task two 24-byte extension results and six 4-byte lists per
     # extension, each array rounded up to 256 bytes, 4,352 fixed bytes, and
-    # the resume states of the 128-, 256- and 512-cell windows (64 << t rows,
-    # t = 1..3): 2n / (16, 32, 256) states of 64 + 8 * rows bytes, each pool
-    # rounded up to 256 bytes
+    # the resume states of the 64-, 128-, 256- and 512-cell windows (64 << t
+    # rows, t = 0..3): 2n / (8, 16, 32, 256) states of 64 + 8 * rows bytes,
+    # each pool rounded up to 256 bytes
     lib = _lib.load()
     for n in (0, 1, 2, 5, 31, 32, 33, 1000, 12345, 10**6):
         want = _al(48 * n) + 6 * _al(8 * n) + 4352
-        for t, div in ((1, 16), (2, 32), (3, 256)):
+        for t, div in ((0, 8), (1, 16), (2, 32), (3, 256)):
             want += _al(-(-2 * n // div) * (64 + 8 * (64 << t)))
         assert lib.xd_batch_scratch_bytes(None, n, None) == want, n
     bad = _lib.Tuning(3, 0, 0, 0, 0, 0)  # waves_per_cu must be a multiple of 4
