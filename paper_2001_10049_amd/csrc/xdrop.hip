@@ -397,10 +397,11 @@ __global__ __launch_bounds__(64) void k_ext_first(BatchArgs A, uint32_t e0, uint
 // SAVE: leave the state of what overflows (for the next window to resume);
 // RESUME: take such states from in_list.
 // (the 128-cell window's queue segment, which saves nothing, is held to 80
-// VGPRs, 6 waves per SIMD; its list, which resumes and saves, to 96, 5 waves)
+// VGPRs, 6 waves per SIMD; its list, which resumes and saves, to 96, 5 waves;
+// the 512-cell window, in groups of 2 antidiagonals, to 128, 4 waves)
 template <int CPL, int GS, bool UNIT, int WAVES, bool SAVE, bool RESUME>
 __global__ __launch_bounds__(64 * WAVES)
-__attribute__((amdgpu_waves_per_eu(CPL == 2 ? (SAVE ? 5 : 6) : 1)))
+__attribute__((amdgpu_waves_per_eu(CPL == 2 ? (SAVE ? 5 : 6) : CPL == 8 ? 4 : 1)))
 void k_ext_tier(const TierArgs* __restrict__ P) {
   static_assert(WAVES * xd::Tier<CPL, GS>::LDS_WORDS * 4 <= 64 * 1024, "LDS per block");
   __shared__ uint32_t rings[WAVES][xd::Tier<CPL, GS>::LDS_WORDS];
@@ -1128,7 +1129,7 @@ void launch_wide(const Scratch& S, uint32_t blocks, hipStream_t stream, bool seg
                      stream, ta + 1);
   hipLaunchKernelGGL((k_ext_tier<4, 4, UNIT, 4, true, true>), dim3(blocks), dim3(256), 0,
                      stream, ta + 2);
-  hipLaunchKernelGGL((k_ext_tier<8, 4, UNIT, 2, true, true>), dim3(2 * blocks), dim3(128), 0,
+  hipLaunchKernelGGL((k_ext_tier<8, 2, UNIT, 2, true, true>), dim3(2 * blocks), dim3(128), 0,
                      stream, ta + 3);
   hipLaunchKernelGGL((k_ext_tier<16, 2, UNIT, 1, false, true>), dim3(4 * blocks), dim3(64), 0,
                      stream, ta + 4);
