@@ -37,6 +37,7 @@
 #include "scan.h"
 #include "store_view.h"
 #include "xdrop_device.h"
+#include "pair2_device.h"
 #include "pair_device.h"
 
 using xd::ExtOut;
@@ -54,7 +55,7 @@ __device__ unsigned long long* g_buf;
 __device__ uint32_t g_cap;
 __device__ uint32_t g_n;
 // kernel tags (k_ext_tier<CPL, ...> records kTier + CPL)
-enum : uint32_t { kFirst = 1, kPair = 0x20, kTier = 0x40, kBand = 0x80 };
+enum : uint32_t { kFirst = 1, kPair = 0x20, kPair2 = 0x21, kTier = 0x40, kBand = 0x80 };
 __device__ __forceinline__ uint64_t now() { return (uint64_t)wall_clock64(); }
 __device__ __forceinline__ void record(uint32_t tag, uint64_t t0, uint32_t items) {
   if ((threadIdx.x & 63) != 0) return;
@@ -434,8 +435,9 @@ void k_ext_tier(const TierArgs* __restrict__ P) {
 #endif
     if (!run_ext<CPL, GS, UNIT, SAVE, RESUME>(Q.A, e, rings[w], resume)) {
       const TierArgs& R = *pp;
-      overflow_to(R.A.ext, R.out_list, R.out_count, R.out_state, R.out_cap, R.out_rec, e,
-                  rings[w]);
+      // (a kernel that saves nothing leaves no state to keep)
+      overflow_to(R.A.ext, R.out_list, R.out_count, SAVE ? R.out_state : nullptr, R.out_cap,
+                  R.out_rec, e, rings[w]);
     }
   }
   XD_STAMP(stamps::kTier + CPL, taken);
@@ -518,6 +520,28 @@ void k_pair_tier(const TierArgs* __restrict__ P,
   XD_STAMP_T0();
   xd::pair::run(W, lds[w], Zp);
   XD_STAMP(stamps::kPair, W.taken);
+}
+
+// The batched form's 128-cell queue segment for match = 1 with two
+// extensions per wave (xd::pair2): the extensions whose X starts them in the
+// 128-cell window.  What outgrows it leaves its state for the 256-cell
+// window.
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_pair2_tier(const TierArgs* __restrict__ P,
+                                                           const xd::pair::Shared* Zp) {
+  static_assert(WAVES * xd::pair2::WAVE_WORDS * 4 <= 64 * 1024, "LDS per block");
+  __shared__ uint32_t lds[WAVES][xd::pair2::WAVE_WORDS];
+  const int w = threadIdx.x >> 6;
+  const TierArgs& Q = *P;
+  PairWork W;
+  W.pp = P;
+  W.seg_lo = Q.seg ? __builtin_amdgcn_readfirstlane(Q.seg[0]) : 0u;
+  W.seg_len = Q.seg ? __builtin_amdgcn_readfirstlane(Q.seg[1]) - W.seg_lo : 0u;
+  W.n_in = Q.in_count ? __builtin_amdgcn_readfirstlane(*Q.in_count) : 0u;
+  if (W.seg_len + W.n_in == 0) return;  // no work: leave without touching the shared head
+  XD_STAMP_T0();
+  xd::pair2::run(W, lds[w], Zp);
+  XD_STAMP(stamps::kPair2, W.taken);
 }
 
 // Band tier: persistent workgroups of kBandWaves waves, each taking the next
@@ -1106,10 +1130,14 @@ TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
     T.out_rec = t <= 3 ? (uint32_t)resume_rec(t) : 0u;
     T.pad = 0;
   }
+  // the 128-cell queue segment starts its extensions; the packed kernel that
+  // runs it (match = 1) leaves the state of what outgrows it in pool 1, as
+  // the 128-cell list does (the two share that list and its slots)
   p.t[6].in_state = nullptr;
   p.t[6].in_rec = 0u;
-  p.t[6].out_state = nullptr;
-  p.t[6].out_cap = 0u;
+  p.t[6].out_state = S.state[1];
+  p.t[6].out_cap = S.state_cap[1];
+  p.t[6].out_rec = (uint32_t)resume_rec(1);
   p.pz = pair_shared(A.sc);
   return p;
 }
@@ -1120,9 +1148,13 @@ TierPack make_pack(const BatchArgs& A, const Scratch& S, bool segs) {
 // and save, 1024 resumes; the 128-cell queue segment starts its extensions
 // and saves nothing.
 template <bool UNIT>
-void launch_wide(const Scratch& S, uint32_t blocks, hipStream_t stream, bool segs) {
+void launch_wide(const Scratch& S, uint32_t blocks, hipStream_t stream, bool segs,
+                 bool packed) {
   const TierArgs* ta = (const TierArgs*)S.targs;
-  if (segs)
+  if (segs && packed)
+    hipLaunchKernelGGL((k_pair2_tier<4>), dim3(blocks), dim3(256), 0, stream, ta + 6,
+                       &((const TierPack*)S.targs)->pz);
+  else if (segs)
     hipLaunchKernelGGL((k_ext_tier<2, 8, UNIT, 4, false, false>), dim3(blocks), dim3(256), 0,
                        stream, ta + 6);
   hipLaunchKernelGGL((k_ext_tier<2, 8, UNIT, 4, true, true>), dim3(blocks), dim3(256), 0,
@@ -1155,7 +1187,7 @@ void launch_plain_ext(const BatchArgs& A, const Scratch& S, uint64_t n_ext, hipE
                        (uint32_t)e0, S.ovf[0], S.ctr + kOvfCount + 0);
   }
   if (ev) (void)hipEventRecord(ev[1], stream);
-  launch_wide<UNIT>(S, kWideBlocks / 4, stream, false);
+  launch_wide<UNIT>(S, kWideBlocks / 4, stream, false, false);
   if (ev) (void)hipEventRecord(ev[2], stream);
 }
 
@@ -1188,7 +1220,7 @@ void launch_persistent_ext(const BatchArgs& A, const Scratch& S, uint64_t n_ext,
   else
     launch_tier0<UNIT, 8>(S, blocks, stream);
   if (ev) (void)hipEventRecord(ev[1], stream);
-  launch_wide<UNIT>(S, blocks, stream, true);
+  launch_wide<UNIT>(S, blocks, stream, true, UNIT && pair_ok(A.sc));
   if (ev) (void)hipEventRecord(ev[2], stream);
 }
 
