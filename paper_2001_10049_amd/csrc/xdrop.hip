@@ -525,10 +525,12 @@ void k_pair_tier(const TierArgs* __restrict__ P,
 // The batched form's 128-cell queue segment for match = 1 with two
 // extensions per wave (xd::pair2): the extensions whose X starts them in the
 // 128-cell window.  What outgrows it leaves its state for the 256-cell
-// window.
+// window.  (Held to 96 VGPRs, 5 waves per SIMD: the few values that then
+// spill are read only on the extension start and overflow paths; 117
+// unconstrained gave 4 waves and a 4 % slower c3.)
 template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_pair2_tier(const TierArgs* __restrict__ P,
-                                                           const xd::pair::Shared* Zp) {
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(5)))
+void k_pair2_tier(const TierArgs* __restrict__ P, const xd::pair::Shared* Zp) {
   static_assert(WAVES * xd::pair2::WAVE_WORDS * 4 <= 64 * 1024, "LDS per block");
   __shared__ uint32_t lds[WAVES][xd::pair2::WAVE_WORDS];
   const int w = threadIdx.x >> 6;
