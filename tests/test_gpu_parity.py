@@ -246,6 +246,24 @@ def test_persistent_parity(name, tuning):
     assert_same(got, oracle.align_workload(w), label="persistent " + name)
 
 
+@pytest.mark.parametrize("wl", ["edge", "band", "flank"])
+def test_packed_128_window_parity(wl):
+    # every extension with 1 < X <= 5000 starts in the 128-cell window, which
+    # the batched form runs in the packed two-extension kernel for +1/-1/-1:
+    # walls, reads of length k, early exits, X up to its limit and past it,
+    # bands that outgrow it (their state resumes in the 256-cell window)
+    w = {"edge": edge_workload, "band": band_workload, "flank": random_flank_workload}[wl]()
+    print("packed 128", wl, flush=True)
+    store = xd.ReadStore.from_workload(w)
+    pairs, seeds, x = xd.workload_tensors(w, "cuda")
+    out = xd.align_batch(store, pairs, seeds, x=x, k=w.k, persistent=True,
+                         tuning=dict(x_tier1=1, x_tier2=5000))
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    store.close()
+    assert_same(got, oracle.align_workload(w), label="packed 128 " + wl)
+
+
 def test_persistent_edge_and_scoring():
     w = edge_workload()
     store = xd.ReadStore.from_workload(w)
