@@ -398,11 +398,12 @@ __global__ __launch_bounds__(64) void k_ext_first(BatchArgs A, uint32_t e0, uint
 // SAVE: leave the state of what overflows (for the next window to resume);
 // RESUME: take such states from in_list.
 // (the 128-cell window's queue segment, which saves nothing, is held to 80
-// VGPRs, 6 waves per SIMD; its list, which resumes and saves, to 96, 5 waves;
-// the 512-cell window, in groups of 2 antidiagonals, to 128, 4 waves)
+// VGPRs, 6 waves per SIMD; its list, which resumes and saves, and the
+// 256-cell window to 96, 5 waves; the 512-cell window, in groups of 2
+// antidiagonals, to 128, 4 waves; none of them spills a vector register)
 template <int CPL, int GS, bool UNIT, int WAVES, bool SAVE, bool RESUME>
 __global__ __launch_bounds__(64 * WAVES)
-__attribute__((amdgpu_waves_per_eu(CPL == 2 ? (SAVE ? 5 : 6) : CPL == 8 ? 4 : 1)))
+__attribute__((amdgpu_waves_per_eu(CPL == 2 ? (SAVE ? 5 : 6) : CPL == 4 ? 5 : CPL == 8 ? 4 : 1)))
 void k_ext_tier(const TierArgs* __restrict__ P) {
   static_assert(WAVES * xd::Tier<CPL, GS>::LDS_WORDS * 4 <= 64 * 1024, "LDS per block");
   __shared__ uint32_t rings[WAVES][xd::Tier<CPL, GS>::LDS_WORDS];
