@@ -38,6 +38,7 @@
 #include "store_view.h"
 #include "xdrop_device.h"
 #include "pair2_device.h"
+#include "pair4_device.h"
 #include "pair_device.h"
 
 using xd::ExtOut;
@@ -55,7 +56,7 @@ __device__ unsigned long long* g_buf;
 __device__ uint32_t g_cap;
 __device__ uint32_t g_n;
 // kernel tags (k_ext_tier<CPL, ...> records kTier + CPL)
-enum : uint32_t { kFirst = 1, kPair = 0x20, kPair2 = 0x21, kTier = 0x40, kBand = 0x80 };
+enum : uint32_t { kFirst = 1, kPair = 0x20, kPair2 = 0x21, kPair4 = 0x22, kTier = 0x40, kBand = 0x80 };
 __device__ __forceinline__ uint64_t now() { return (uint64_t)wall_clock64(); }
 __device__ __forceinline__ void record(uint32_t tag, uint64_t t0, uint32_t items) {
   if ((threadIdx.x & 63) != 0) return;
@@ -466,6 +467,37 @@ struct PairWork {
       R.A.ext[e] = o;
     }
   }
+  // the next extension and, for a flagged entry of the overflow list, the
+  // state the narrower window left (null otherwise); X above the packed
+  // limit goes on to the next tier (from its seed)
+  __device__ bool next(uint32_t& e, xd::Ext& ex, const uint8_t*& rs) {
+    for (;;) {
+      const TierArgs& Q = *pp;
+      uint32_t idx = 0;
+      if (xd::lane_id() == 0) idx = atomicAdd(Q.head, 1u);
+      idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
+      if (idx >= seg_len + n_in) return false;
+      const uint32_t raw = __builtin_amdgcn_readfirstlane(
+          idx < seg_len ? Q.queue[seg_lo + idx] : Q.in_list[idx - seg_len]);
+      e = raw & ~kResumeFlag;
+      rs = raw & kResumeFlag ? Q.in_state + (uint64_t)(idx - seg_len) * Q.in_rec : nullptr;
+      if (!make_ext(Q.A, e, ex)) {
+        if (xd::lane_id() == 0) {
+          ExtOut o = {0, 0, 0, xd::kExtInvalid, 0};
+          Q.A.ext[e] = o;
+        }
+        continue;
+      }
+      if (ex.X > xd::pair::kXMax) {
+        overflow(e);
+        continue;
+      }
+#ifdef XD_WAVE_STAMPS
+      ++taken;
+#endif
+      return true;
+    }
+  }
   // one whose band outgrew the window, its state at state (LDS)
   __device__ void overflow(uint32_t e, const uint32_t* state) {
     const TierArgs& R = *pp;
@@ -545,6 +577,31 @@ void k_pair2_tier(const TierArgs* __restrict__ P, const xd::pair::Shared* Zp) {
   XD_STAMP_T0();
   xd::pair2::run(W, lds[w], Zp);
   XD_STAMP(stamps::kPair2, W.taken);
+}
+
+// The batched form's 256-cell window for match = 1 with two extensions per
+// wave (xd::pair4): its queue segment, then what outgrew the 128-cell window
+// (resumed from the state it left, else from the seed).  What outgrows it
+// leaves its state for the 512-cell window.  (Held to 128 VGPRs, 4 waves
+// per SIMD, which is also what its LDS allows; the few spilled values are
+// read only on the extension start and overflow paths.)
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(4)))
+void k_pair4_tier(const TierArgs* __restrict__ P,
+                                                           const xd::pair::Shared* Zp) {
+  static_assert(WAVES * xd::pair4::WAVE_WORDS * 4 <= 64 * 1024, "LDS per block");
+  __shared__ uint32_t lds[WAVES][xd::pair4::WAVE_WORDS];
+  const int w = threadIdx.x >> 6;
+  const TierArgs& Q = *P;
+  PairWork W;
+  W.pp = P;
+  W.seg_lo = Q.seg ? __builtin_amdgcn_readfirstlane(Q.seg[0]) : 0u;
+  W.seg_len = Q.seg ? __builtin_amdgcn_readfirstlane(Q.seg[1]) - W.seg_lo : 0u;
+  W.n_in = Q.in_count ? __builtin_amdgcn_readfirstlane(*Q.in_count) : 0u;
+  if (W.seg_len + W.n_in == 0) return;  // no work: leave without touching the shared head
+  XD_STAMP_T0();
+  xd::pair4::run(W, lds[w], Zp);
+  XD_STAMP(stamps::kPair4, W.taken);
 }
 
 // Band tier: persistent workgroups of kBandWaves waves, each taking the next
@@ -1162,8 +1219,12 @@ void launch_wide(const Scratch& S, uint32_t blocks, hipStream_t stream, bool seg
                        stream, ta + 6);
   hipLaunchKernelGGL((k_ext_tier<2, 8, UNIT, 4, true, true>), dim3(blocks), dim3(256), 0,
                      stream, ta + 1);
-  hipLaunchKernelGGL((k_ext_tier<4, 4, UNIT, 4, true, true>), dim3(blocks), dim3(256), 0,
-                     stream, ta + 2);
+  if (packed)
+    hipLaunchKernelGGL((k_pair4_tier<4>), dim3(blocks), dim3(256), 0, stream, ta + 2,
+                       &((const TierPack*)S.targs)->pz);
+  else
+    hipLaunchKernelGGL((k_ext_tier<4, 4, UNIT, 4, true, true>), dim3(blocks), dim3(256), 0,
+                       stream, ta + 2);
   hipLaunchKernelGGL((k_ext_tier<8, 2, UNIT, 2, true, true>), dim3(2 * blocks), dim3(128), 0,
                      stream, ta + 3);
   hipLaunchKernelGGL((k_ext_tier<16, 2, UNIT, 1, false, true>), dim3(4 * blocks), dim3(64), 0,

@@ -32,7 +32,7 @@ import time
 import numpy as np
 
 TAGS = {0x01: "k_ext_first<1,16>", 0x20: "k_pair_tier<4>", 0x21: "k_pair2_tier<4>",
-        0x80: "k_ext_band"}
+        0x22: "k_pair4_tier<4>", 0x80: "k_ext_band"}
 for _c in (1, 2, 4, 8, 16):
     TAGS[0x40 + _c] = "k_ext_tier<%d,...>" % _c
 PERSISTENT_TAGS = {t for t in TAGS if t != 0x01}
