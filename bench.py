@@ -60,7 +60,7 @@ def kernel_source_hash() -> str:
     """Hash of the sources the extension kernels and their launches are built from."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2001_10049_amd", "csrc")
-    for f in ("xdrop.hip", "xdrop_device.h", "pair_device.h", "pair2_device.h"):
+    for f in ("xdrop.hip", "xdrop_device.h", "pair_device.h", "pair2_device.h", "pair4_device.h"):
         h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
