@@ -395,6 +395,72 @@ __device__ __forceinline__ void live_masks(Slot& S, uint32_t U1e, uint32_t U1o, 
   }
 }
 
+// Starts extension e in slot H from the state a narrower window saved (rs:
+// a ResumeHead and its rows, 32-bit units), converted as in pair4::start:
+// live U become v = U - Rs with Rs = thr32 - (1024 + g), so the threshold is
+// 1024 + g, and Rs - 7168 plus the state's rebases become the slot's rebase
+// total.
+template <int H>
+__device__ __forceinline__ void resume(Slot& S, const Shared* Zp, uint32_t* lds, uint32_t e,
+                                       const Ext& ex, const uint8_t* rs, uint32_t& U1e,
+                                       uint32_t& U1o, uint32_t& Upe, uint32_t& Upo,
+                                       uint32_t& cnt, uint32_t& NT, uint32_t& KX) {
+  const int lane = lane_id();
+  uint32_t* cold = slot_cold<H>(lds);
+  const ResumeHead* Hd = (const ResumeHead*)rs;
+  const int32_t g = (int32_t)pair::uni((uint32_t)Zp->g);
+  const int32_t thr32 = (int32_t)pair::uni((uint32_t)Hd->thr);
+  const int32_t qp = (int32_t)pair::uni((uint32_t)Hd->q_rows);
+  const uint32_t tp = pair::uni((uint32_t)Hd->top_prev);
+  const uint32_t rsub = (uint32_t)(thr32 - (kBase + g));
+  S.active = 1;
+  S.d = (int32_t)pair::uni((uint32_t)Hd->d);
+  S.base = (int32_t)pair::uni((uint32_t)Hd->base);
+  S.bi = (int32_t)pair::uni((uint32_t)Hd->bi);
+  S.dstar = (int32_t)pair::uni((uint32_t)Hd->dstar);
+  S.m = ex.m;
+  S.n = ex.n;
+  const uint64_t c0 = Hd->cells;
+  S.cnt32 = (uint32_t)(c0 >> 6) + ((uint64_t)lane < (c0 & 63) ? 1u : 0u);
+  // rings: the last RING positions of b up to one chunk past the next
+  // group's, and the window's rows of a (the next refill of each fills the
+  // whole ring)
+  const int32_t fb = ((S.d + GS - S.base) | 63) + 64 - RING;
+  S.filled = max(fb, -1);
+  const int32_t fa = ((S.base + Q - 1) | 63) + 64 - RA;
+  const int32_t filled_a = max(fa, -1);
+  if (lane == 0) {
+    cold[pair::kCe] = e;
+    cold[pair::kCwaLo] = (uint32_t)(uintptr_t)ex.wa;
+    cold[pair::kCwaHi] = (uint32_t)((uintptr_t)ex.wa >> 32);
+    cold[pair::kCwbLo] = (uint32_t)(uintptr_t)ex.wb;
+    cold[pair::kCwbHi] = (uint32_t)((uintptr_t)ex.wb >> 32);
+    cold[pair::kCoa] = (uint32_t)ex.oa;
+    cold[pair::kCob] = (uint32_t)ex.ob;
+    cold[pair::kCdir] = (uint32_t)ex.dir;
+    cold[pair::kCdirb] = (uint32_t)ex.dirb;
+    cold[pair::kCcomp] = ex.comp;
+    cold[pair::kCfilledA] = (uint32_t)filled_a;
+    cold[pair::kCR] = rsub - 7168u + (uint32_t)Hd->rebased;
+  }
+  wave_lds_fence();
+  const int32_t* u1s = (const int32_t*)(rs + sizeof(ResumeHead));
+  const int32_t* ups = u1s + qp;
+  auto conv = [&](int32_t u) -> uint32_t { return u ? kPat + (uint32_t)u - rsub : 0u; };
+  const int32_t qe = 2 * lane, qo = 2 * lane + 1;
+  U1e = pair::with_half<H>(U1e, qe < qp ? conv(u1s[qe]) : 0u);
+  U1o = pair::with_half<H>(U1o, qo < qp ? conv(u1s[qo]) : 0u);
+  Upe = pair::with_half<H>(Upe, qe < qp ? conv(ups[qe]) : qe == qp ? conv((int32_t)tp) : 0u);
+  Upo = pair::with_half<H>(Upo, qo < qp ? conv(ups[qo]) : qo == qp ? conv((int32_t)tp) : 0u);
+  live_masks<H>(S, U1e, U1o, Upe, Upo);
+  cnt = pair::with_half<H>(cnt, 0u);
+  NT = pair::with_half<H>(NT, kNegPat + (uint32_t)(g + kBase - 1));
+  KX = pair::with_half<H>(KX, 0x7fffu - (uint32_t)ex.X);
+  S.pf_b = pair::word_of(ex.wb, ex.ob, ex.dirb, S.filled + 1 + lane, ex.n);
+  S.pf_a = pair::word_of(ex.wa, ex.oa, ex.dir, filled_a + 1 + lane, ex.m);
+  load_a<H>(S, lds);
+}
+
 // Brings slot H to the start of a group (as pair::prepare, rows in pairs).
 template <int H>
 __device__ __forceinline__ int prepare(Slot& S, const Shared* Zp, uint32_t* lds, uint32_t& U1e,
@@ -598,8 +664,9 @@ __device__ __forceinline__ void add_rebase(uint32_t* lds, uint32_t r) {
   wave_lds_fence();
 }
 
-// Runs extensions two at a time until W runs out (the contract of
-// pair::run: W.next, W.done, W.overflow(e, state)).
+// Runs extensions two at a time until W runs out: W.next(e, ex, rs) (rs:
+// a saved state to resume, or null), W.done(e, result), W.overflow(e,
+// state).
 template <class Work>
 __device__ void run(Work& W, uint32_t* lds, const Shared* Zp) {
   Slot A, B;
@@ -629,18 +696,24 @@ __device__ void run(Work& W, uint32_t* lds, const Shared* Zp) {
     if (!A.active && more) {
       uint32_t e;
       Ext ex;
-      if (W.next(e, ex))
-        start<0>(A, Zp, lds, e, ex, U1e, U1o, Upe, Upo, cnt, NT, KX);
-      else
+      const uint8_t* rs;
+      if (!W.next(e, ex, rs))
         more = false;
+      else if (rs)
+        resume<0>(A, Zp, lds, e, ex, rs, U1e, U1o, Upe, Upo, cnt, NT, KX);
+      else
+        start<0>(A, Zp, lds, e, ex, U1e, U1o, Upe, Upo, cnt, NT, KX);
     }
     if (!B.active && more) {
       uint32_t e;
       Ext ex;
-      if (W.next(e, ex))
-        start<1>(B, Zp, lds, e, ex, U1e, U1o, Upe, Upo, cnt, NT, KX);
-      else
+      const uint8_t* rs;
+      if (!W.next(e, ex, rs))
         more = false;
+      else if (rs)
+        resume<1>(B, Zp, lds, e, ex, rs, U1e, U1o, Upe, Upo, cnt, NT, KX);
+      else
+        start<1>(B, Zp, lds, e, ex, U1e, U1o, Upe, Upo, cnt, NT, KX);
     }
     if (!A.active && !B.active) break;
     int sa = A.active ? prepare<0>(A, Zp, lds, U1e, U1o, Upe, Upo) : kGo;

@@ -555,10 +555,11 @@ void k_pair_tier(const TierArgs* __restrict__ P,
   XD_STAMP(stamps::kPair, W.taken);
 }
 
-// The batched form's 128-cell queue segment for match = 1 with two
-// extensions per wave (xd::pair2): the extensions whose X starts them in the
-// 128-cell window.  What outgrows it leaves its state for the 256-cell
-// window.  (Held to 96 VGPRs, 5 waves per SIMD: the few values that then
+// The batched form's 128-cell window for match = 1 with two extensions per
+// wave (xd::pair2), in two launches: its queue segment (the extensions whose
+// X starts them there), then its list (what outgrew the 64-cell window,
+// resumed from the state it left, else from the seed).  What outgrows it
+// leaves its state for the 256-cell window.  (Held to 96 VGPRs, 5 waves per SIMD: the few values that then
 // spill are read only on the extension start and overflow paths; 117
 // unconstrained gave 4 waves and a 4 % slower c3.)
 template <int WAVES>
@@ -1217,8 +1218,12 @@ void launch_wide(const Scratch& S, uint32_t blocks, hipStream_t stream, bool seg
   else if (segs)
     hipLaunchKernelGGL((k_ext_tier<2, 8, UNIT, 4, false, false>), dim3(blocks), dim3(256), 0,
                        stream, ta + 6);
-  hipLaunchKernelGGL((k_ext_tier<2, 8, UNIT, 4, true, true>), dim3(blocks), dim3(256), 0,
-                     stream, ta + 1);
+  if (packed)
+    hipLaunchKernelGGL((k_pair2_tier<4>), dim3(blocks), dim3(256), 0, stream, ta + 1,
+                       &((const TierPack*)S.targs)->pz);
+  else
+    hipLaunchKernelGGL((k_ext_tier<2, 8, UNIT, 4, true, true>), dim3(blocks), dim3(256), 0,
+                       stream, ta + 1);
   if (packed)
     hipLaunchKernelGGL((k_pair4_tier<4>), dim3(blocks), dim3(256), 0, stream, ta + 2,
                        &((const TierPack*)S.targs)->pz);
