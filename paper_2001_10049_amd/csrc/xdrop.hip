@@ -506,31 +506,11 @@ struct PairWork {
   __device__ void done(uint32_t e, const ExtOut& o) {
     if (xd::lane_id() == 0) pp->A.ext[e] = o;
   }
+  // the next extension for a tier that resumes nothing (its entries carry
+  // no state)
   __device__ bool next(uint32_t& e, xd::Ext& ex) {
-    for (;;) {
-      const TierArgs& Q = *pp;
-      uint32_t idx = 0;
-      if (xd::lane_id() == 0) idx = atomicAdd(Q.head, 1u);
-      idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
-      if (idx >= seg_len + n_in) return false;
-      e = __builtin_amdgcn_readfirstlane(idx < seg_len ? Q.queue[seg_lo + idx]
-                                                       : Q.in_list[idx - seg_len]);
-      if (!make_ext(Q.A, e, ex)) {
-        if (xd::lane_id() == 0) {
-          ExtOut o = {0, 0, 0, xd::kExtInvalid, 0};
-          Q.A.ext[e] = o;
-        }
-        continue;
-      }
-      if (ex.X > xd::pair::kXMax) {
-        overflow(e);
-        continue;
-      }
-#ifdef XD_WAVE_STAMPS
-      ++taken;
-#endif
-      return true;
-    }
+    const uint8_t* rs;
+    return next(e, ex, rs);
   }
 };
 
