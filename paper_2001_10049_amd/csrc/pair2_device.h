@@ -62,13 +62,16 @@ struct Slot {
   uint32_t cnt32;       // per lane: evaluated cells flushed from the binary16 counter
 };
 
+using Geo = pair::Geometry<RING, MIR, RA>;
+static_assert(Geo::WAVE_WORDS == WAVE_WORDS, "geometry");
+
 template <int H>
 __device__ __forceinline__ uint32_t* slot_ring(uint32_t* lds) {
-  return lds + H * SLOT_WORDS;
+  return pair::slot_ring<H, Geo>(lds);
 }
 template <int H>
 __device__ __forceinline__ uint32_t* slot_cold(uint32_t* lds) {
-  return lds + 2 * SLOT_WORDS + H * kCWords;
+  return pair::slot_cold<H, Geo>(lds);
 }
 
 // ---- the packed step ------------------------------------------------------
@@ -192,31 +195,6 @@ __device__ __forceinline__ int32_t low_row(uint64_t Me, uint64_t Mo) {
   return (int32_t)min(le, lo);
 }
 
-// b ring of slot H up to at least j = jhi (see pair::fill_b)
-template <int H>
-__device__ __forceinline__ void fill_b(Slot& S, const Shared* Zp, uint32_t* lds, int32_t jhi) {
-  uint32_t* ring = slot_ring<H>(lds);
-  const uint32_t* cold = slot_cold<H>(lds);
-  const uint32_t* wb = pair::cold_ptr(cold, pair::kCwbLo);
-  const int32_t ob = (int32_t)pair::cold_get(cold, pair::kCob);
-  const int32_t dirb = (int32_t)pair::cold_get(cold, pair::kCdirb);
-  const uint32_t comp = pair::cold_get(cold, pair::kCcomp);
-  const uint32_t ringw = Zp->ringw, dM = Zp->dM;
-  const int lane = lane_id();
-  while (S.filled < jhi) {
-    const int32_t j = S.filled + 1 + lane;
-    const uint32_t v = (j >= 1 & j <= S.n)
-                           ? ringw + (dM << (8u * (pair::code_in(S.pf_b, ob, dirb, j) ^ comp)))
-                           : 0u;
-    const int slot = j & MASK;
-    ring[slot] = v;
-    if (slot < MIR) ring[RING + slot] = v;
-    S.pf_b = pair::word_of(wb, ob, dirb, j + 64, S.n);
-    S.filled += 64;
-  }
-  wave_lds_fence();
-}
-
 // a ring of slot H holding rows base .. base + 127 (a refill writes the
 // chunk after too), and each lane's a-code byte offsets of its two rows
 // added to its ring's LDS byte address
@@ -254,22 +232,7 @@ __device__ __forceinline__ void start(Slot& S, const Shared* Zp, uint32_t* lds, 
                                       uint32_t& Upe, uint32_t& Upo, uint32_t& cnt, uint32_t& NT,
                                       uint32_t& KX) {
   const int lane = lane_id();
-  uint32_t* cold = slot_cold<H>(lds);
-  if (lane == 0) {
-    cold[pair::kCe] = e;
-    cold[pair::kCwaLo] = (uint32_t)(uintptr_t)ex.wa;
-    cold[pair::kCwaHi] = (uint32_t)((uintptr_t)ex.wa >> 32);
-    cold[pair::kCwbLo] = (uint32_t)(uintptr_t)ex.wb;
-    cold[pair::kCwbHi] = (uint32_t)((uintptr_t)ex.wb >> 32);
-    cold[pair::kCoa] = (uint32_t)ex.oa;
-    cold[pair::kCob] = (uint32_t)ex.ob;
-    cold[pair::kCdir] = (uint32_t)ex.dir;
-    cold[pair::kCdirb] = (uint32_t)ex.dirb;
-    cold[pair::kCcomp] = ex.comp;
-    cold[pair::kCfilledA] = 0xffffffffu;  // -1
-    cold[pair::kCR] = 0;
-  }
-  wave_lds_fence();
+  pair::cold_start<H, Geo>(lds, e, ex, 0xffffffffu, 0u);  // a ring empty: filled to row -1
   S.active = 1;
   S.d = 0;
   S.base = 0;
@@ -307,20 +270,6 @@ __device__ __forceinline__ void park(uint32_t& U1e, uint32_t& U1o, uint32_t& Upe
 }
 
 // The finished extension's result.
-template <int H>
-__device__ __forceinline__ ExtOut result(const Slot& S, const Shared* Zp, uint32_t* lds,
-                                         uint32_t cnt, uint32_t NT) {
-  const uint64_t cells = wave_sum_u64v((uint64_t)S.cnt32 + pair::count_half<H>(cnt));
-  const int32_t thr = pair::half_of<H>(NT) - (int32_t)kNegPat + 1;  // for antidiagonal d + 1
-  ExtOut o;
-  o.best = thr - Zp->g * (S.d + 1) - kBase +
-           (int32_t)pair::cold_get(slot_cold<H>(lds), pair::kCR);
-  o.bi = S.bi;
-  o.bj = S.dstar - S.bi;
-  o.flags = kExtDone;
-  o.cells = cells;
-  return o;
-}
 
 // Slot H's state where its band outgrew the window, in the 32-bit tiers'
 // units (as pair::save; 128 rows: row 2l from the even register of lane l,
@@ -406,7 +355,6 @@ __device__ __forceinline__ void resume(Slot& S, const Shared* Zp, uint32_t* lds,
                                        uint32_t& U1o, uint32_t& Upe, uint32_t& Upo,
                                        uint32_t& cnt, uint32_t& NT, uint32_t& KX) {
   const int lane = lane_id();
-  uint32_t* cold = slot_cold<H>(lds);
   const ResumeHead* Hd = (const ResumeHead*)rs;
   const int32_t g = (int32_t)pair::uni((uint32_t)Zp->g);
   const int32_t thr32 = (int32_t)pair::uni((uint32_t)Hd->thr);
@@ -429,21 +377,8 @@ __device__ __forceinline__ void resume(Slot& S, const Shared* Zp, uint32_t* lds,
   S.filled = max(fb, -1);
   const int32_t fa = ((S.base + Q - 1) | 63) + 64 - RA;
   const int32_t filled_a = max(fa, -1);
-  if (lane == 0) {
-    cold[pair::kCe] = e;
-    cold[pair::kCwaLo] = (uint32_t)(uintptr_t)ex.wa;
-    cold[pair::kCwaHi] = (uint32_t)((uintptr_t)ex.wa >> 32);
-    cold[pair::kCwbLo] = (uint32_t)(uintptr_t)ex.wb;
-    cold[pair::kCwbHi] = (uint32_t)((uintptr_t)ex.wb >> 32);
-    cold[pair::kCoa] = (uint32_t)ex.oa;
-    cold[pair::kCob] = (uint32_t)ex.ob;
-    cold[pair::kCdir] = (uint32_t)ex.dir;
-    cold[pair::kCdirb] = (uint32_t)ex.dirb;
-    cold[pair::kCcomp] = ex.comp;
-    cold[pair::kCfilledA] = (uint32_t)filled_a;
-    cold[pair::kCR] = rsub - 7168u + (uint32_t)Hd->rebased;
-  }
-  wave_lds_fence();
+  pair::cold_start<H, Geo>(lds, e, ex, (uint32_t)filled_a,
+                          rsub - 7168u + (uint32_t)Hd->rebased);
   const int32_t* u1s = (const int32_t*)(rs + sizeof(ResumeHead));
   const int32_t* ups = u1s + qp;
   auto conv = [&](int32_t u) -> uint32_t { return u ? kPat + (uint32_t)u - rsub : 0u; };
@@ -481,7 +416,7 @@ __device__ __forceinline__ int prepare(Slot& S, const Shared* Zp, uint32_t* lds,
     const int32_t G = full ? GS : kShort;
     const int32_t dv = S.d - S.base;
     if (S.filled < dv + G) {
-      fill_b<H>(S, Zp, lds, S.d + GS - S.base + 64);
+      pair::fill_b<H, Geo>(S, Zp, lds, S.d + GS - S.base + 64);
       continue;
     }
     const int32_t room_a = S.m - S.base - hi, room_b = S.base + lo - S.d + S.n;
@@ -600,25 +535,10 @@ __device__ __forceinline__ void group(Slot& A, Slot& B, uint32_t& U1e, uint32_t&
   }
 }
 
-struct FastOps {
-  int32_t mb, nb, fb;
-};
-
-__device__ __forceinline__ FastOps fast_ops(const Slot& S) {
-  FastOps f;
-  if (S.active) {
-    f.mb = S.m - S.base - (Q - 1) - GS;
-    f.nb = S.n - GS - (S.d - S.base);
-    f.fb = S.filled - (S.d - S.base) - GS;
-  } else {
-    f.mb = f.nb = f.fb = kFar;
-  }
-  return f;
-}
 
 // fast test value of one slot (negative: not fast); z = distance of the top
 // live row from the window top, lo = lowest live row
-__device__ __forceinline__ int32_t fast_test(const Slot& S, const FastOps& f, int32_t& z,
+__device__ __forceinline__ int32_t fast_test(const Slot& S, const pair::FastOps& f, int32_t& z,
                                              int32_t& lo) {
   z = top_gap(S.Me, S.Mo);
   lo = low_row(S.Me, S.Mo);
@@ -629,7 +549,7 @@ __device__ __forceinline__ int32_t fast_test(const Slot& S, const FastOps& f, in
 template <int H>
 __device__ __forceinline__ bool fix(Slot& S, const Shared* Zp, uint32_t* lds, uint32_t& U1e,
                                     uint32_t& U1o, uint32_t& Upe, uint32_t& Upo, int32_t z,
-                                    int32_t lo, FastOps& f) {
+                                    int32_t lo, pair::FastOps& f) {
   if (!S.active) return false;
   if (z < GS) {
     const int32_t sl = lo >> 1;
@@ -643,26 +563,12 @@ __device__ __forceinline__ bool fix(Slot& S, const Shared* Zp, uint32_t* lds, ui
   }
   if (((z + f.mb) | (lo + f.nb)) < 0) return false;
   if (f.fb < 0) {
-    fill_b<H>(S, Zp, lds, S.d + GS - S.base + 64);
+    pair::fill_b<H, Geo>(S, Zp, lds, S.d + GS - S.base + 64);
     f.fb = S.filled - (S.d - S.base) - GS;
   }
   return true;
 }
 
-template <int H>
-__device__ __forceinline__ uint32_t rebase_amount(const Slot& S, int32_t g, uint32_t NT) {
-  const int32_t thr = pair::half_of<H>(NT) - (int32_t)kNegPat + 1;
-  if (!S.active || thr <= kBase + g) return 0u;
-  return (uint32_t)(thr - (kBase + g));
-}
-
-template <int H>
-__device__ __forceinline__ void add_rebase(uint32_t* lds, uint32_t r) {
-  uint32_t* cold = slot_cold<H>(lds);
-  const uint32_t v = pair::cold_get(cold, pair::kCR) + r;
-  if (lane_id() == 0) cold[pair::kCR] = v;
-  wave_lds_fence();
-}
 
 // Runs extensions two at a time until W runs out: W.next(e, ex, rs) (rs:
 // a saved state to resume, or null), W.done(e, result), W.overflow(e,
@@ -720,12 +626,12 @@ __device__ void run(Work& W, uint32_t* lds, const Shared* Zp) {
     int sb = B.active ? prepare<1>(B, Zp, lds, U1e, U1o, Upe, Upo) : kGo;
     if ((sa | sb) & (kEnd | kOvf)) {
       if (sa & kEnd)
-        W.done(pair::cold_get(slot_cold<0>(lds), pair::kCe), result<0>(A, Zp, lds, cnt, NT));
+        W.done(pair::cold_get(slot_cold<0>(lds), pair::kCe), pair::result<0, Geo>(A, Zp, lds, cnt, NT));
       if (sa & kOvf)
         W.overflow(pair::cold_get(slot_cold<0>(lds), pair::kCe),
                    save<0>(A, lds, U1e, U1o, Upe, Upo, cnt, NT));
       if (sb & kEnd)
-        W.done(pair::cold_get(slot_cold<1>(lds), pair::kCe), result<1>(B, Zp, lds, cnt, NT));
+        W.done(pair::cold_get(slot_cold<1>(lds), pair::kCe), pair::result<1, Geo>(B, Zp, lds, cnt, NT));
       if (sb & kOvf)
         W.overflow(pair::cold_get(slot_cold<1>(lds), pair::kCe),
                    save<1>(B, lds, U1e, U1o, Upe, Upo, cnt, NT));
@@ -746,15 +652,15 @@ __device__ void run(Work& W, uint32_t* lds, const Shared* Zp) {
     if (!A.active) NT = pair::with_half<0>(NT, kNegPat + 1500u);
     if (!B.active) NT = pair::with_half<1>(NT, kNegPat + 1500u);
     {
-      const uint32_t R = rebase_amount<0>(A, g, NT) | (rebase_amount<1>(B, g, NT) << 16);
+      const uint32_t R = pair::rebase_amount<0>(A, g, NT) | (pair::rebase_amount<1>(B, g, NT) << 16);
       if (R) {
         U1e = pair::pk_sub_sat(U1e, R);
         U1o = pair::pk_sub_sat(U1o, R);
         Upe = pair::pk_sub_sat(Upe, R);
         Upo = pair::pk_sub_sat(Upo, R);
         NT -= R;
-        if (R & 0xffffu) add_rebase<0>(lds, R & 0xffffu);
-        if (R >> 16) add_rebase<1>(lds, R >> 16);
+        if (R & 0xffffu) pair::add_rebase<0, Geo>(lds, R & 0xffffu);
+        if (R >> 16) pair::add_rebase<1, Geo>(lds, R >> 16);
       }
     }
     A.cnt32 += pair::count_half<0>(cnt);
@@ -772,7 +678,7 @@ __device__ void run(Work& W, uint32_t* lds, const Shared* Zp) {
       continue;
     }
     // fast loop: up to `stretch` groups, slides and refills done in place
-    FastOps fa = fast_ops(A), fb = fast_ops(B);
+    pair::FastOps fa = pair::fast_ops<Q, GS>(A), fb = pair::fast_ops<Q, GS>(B);
     for (int32_t left = stretch; left > 0; --left) {
       int32_t za, la, zb, lb;
       const int32_t ta = fast_test(A, fa, za, la);

@@ -64,13 +64,16 @@ struct Slot {
   uint32_t cnt32;       // per lane: evaluated cells flushed from the binary16 counter
 };
 
+using Geo = pair::Geometry<RING, MIR, RA>;
+static_assert(Geo::WAVE_WORDS == WAVE_WORDS, "geometry");
+
 template <int H>
 __device__ __forceinline__ uint32_t* slot_ring(uint32_t* lds) {
-  return lds + H * SLOT_WORDS;
+  return pair::slot_ring<H, Geo>(lds);
 }
 template <int H>
 __device__ __forceinline__ uint32_t* slot_cold(uint32_t* lds) {
-  return lds + 2 * SLOT_WORDS + H * kCWords;
+  return pair::slot_cold<H, Geo>(lds);
 }
 
 // ---- the packed step ------------------------------------------------------
@@ -200,31 +203,6 @@ __device__ __forceinline__ bool any_live(const uint64_t (&M)[R]) {
   return o != 0;
 }
 
-// b ring of slot H up to at least j = jhi (see pair::fill_b)
-template <int H>
-__device__ __forceinline__ void fill_b(Slot& S, const Shared* Zp, uint32_t* lds, int32_t jhi) {
-  uint32_t* ring = slot_ring<H>(lds);
-  const uint32_t* cold = slot_cold<H>(lds);
-  const uint32_t* wb = pair::cold_ptr(cold, pair::kCwbLo);
-  const int32_t ob = (int32_t)pair::cold_get(cold, pair::kCob);
-  const int32_t dirb = (int32_t)pair::cold_get(cold, pair::kCdirb);
-  const uint32_t comp = pair::cold_get(cold, pair::kCcomp);
-  const uint32_t ringw = Zp->ringw, dM = Zp->dM;
-  const int lane = lane_id();
-  while (S.filled < jhi) {
-    const int32_t j = S.filled + 1 + lane;
-    const uint32_t v = (j >= 1 & j <= S.n)
-                           ? ringw + (dM << (8u * (pair::code_in(S.pf_b, ob, dirb, j) ^ comp)))
-                           : 0u;
-    const int slot = j & MASK;
-    ring[slot] = v;
-    if (slot < MIR) ring[RING + slot] = v;
-    S.pf_b = pair::word_of(wb, ob, dirb, j + 64, S.n);
-    S.filled += 64;
-  }
-  wave_lds_fence();
-}
-
 // a ring of slot H holding rows base .. base + Q - 1 (a refill writes the
 // chunk after too), and each lane's a-code byte offsets of its rows added to
 // its ring's LDS byte address
@@ -272,26 +250,6 @@ __device__ __forceinline__ void live_masks(Slot& S, const uint32_t (&U1)[R],
   }
 }
 
-template <int H>
-__device__ __forceinline__ void cold_setup(uint32_t* lds, uint32_t e, const Ext& ex) {
-  uint32_t* cold = slot_cold<H>(lds);
-  if (lane_id() == 0) {
-    cold[pair::kCe] = e;
-    cold[pair::kCwaLo] = (uint32_t)(uintptr_t)ex.wa;
-    cold[pair::kCwaHi] = (uint32_t)((uintptr_t)ex.wa >> 32);
-    cold[pair::kCwbLo] = (uint32_t)(uintptr_t)ex.wb;
-    cold[pair::kCwbHi] = (uint32_t)((uintptr_t)ex.wb >> 32);
-    cold[pair::kCoa] = (uint32_t)ex.oa;
-    cold[pair::kCob] = (uint32_t)ex.ob;
-    cold[pair::kCdir] = (uint32_t)ex.dir;
-    cold[pair::kCdirb] = (uint32_t)ex.dirb;
-    cold[pair::kCcomp] = ex.comp;
-    cold[pair::kCfilledA] = 0xffffffffu;  // -1
-    cold[pair::kCR] = 0;
-  }
-  wave_lds_fence();
-}
-
 // Starts extension e in slot H, from its seed or from the state a narrower
 // window saved (rs: a ResumeHead and its rows, 32-bit units).  From the
 // seed: the origin (row 0) is live with value X + 1024, thr = g + 1024.
@@ -304,7 +262,7 @@ __device__ __forceinline__ void start(Slot& S, const Shared* Zp, uint32_t* lds, 
                                       uint32_t (&Up)[R], uint32_t& cnt, uint32_t& NT,
                                       uint32_t& KX) {
   const int lane = lane_id();
-  cold_setup<H>(lds, e, ex);
+  pair::cold_start<H, Geo>(lds, e, ex, 0xffffffffu, 0u);  // a ring empty: filled to row -1
   S.active = 1;
   S.m = ex.m;
   S.n = ex.n;
@@ -385,20 +343,6 @@ __device__ __forceinline__ void park(uint32_t (&U1)[R], uint32_t (&Up)[R], uint3
   KX = pair::with_half<H>(KX, 0x7fffu);
 }
 
-template <int H>
-__device__ __forceinline__ ExtOut result(const Slot& S, const Shared* Zp, uint32_t* lds,
-                                         uint32_t cnt, uint32_t NT) {
-  const uint64_t cells = wave_sum_u64v((uint64_t)S.cnt32 + pair::count_half<H>(cnt));
-  const int32_t thr = pair::half_of<H>(NT) - (int32_t)kNegPat + 1;  // for antidiagonal d + 1
-  ExtOut o;
-  o.best = thr - Zp->g * (S.d + 1) - kBase +
-           (int32_t)pair::cold_get(slot_cold<H>(lds), pair::kCR);
-  o.bi = S.bi;
-  o.bj = S.dstar - S.bi;
-  o.flags = kExtDone;
-  o.cells = cells;
-  return o;
-}
 
 // Slot H's state where its band outgrew the window (as pair::save; row
 // 4l + r from register r of lane l; top_prev is 0 at a group boundary).
@@ -474,7 +418,7 @@ __device__ __forceinline__ int prepare(Slot& S, const Shared* Zp, uint32_t* lds,
     const int32_t G = full ? GS : kShort;
     const int32_t dv = S.d - S.base;
     if (S.filled < dv + G) {
-      fill_b<H>(S, Zp, lds, S.d + GS - S.base + 64);
+      pair::fill_b<H, Geo>(S, Zp, lds, S.d + GS - S.base + 64);
       continue;
     }
     const int32_t room_a = S.m - S.base - hi, room_b = S.base + lo - S.d + S.n;
@@ -602,23 +546,8 @@ __device__ __forceinline__ void group(Slot& A, Slot& B, uint32_t (&U1)[R], uint3
   }
 }
 
-struct FastOps {
-  int32_t mb, nb, fb;
-};
 
-__device__ __forceinline__ FastOps fast_ops(const Slot& S) {
-  FastOps f;
-  if (S.active) {
-    f.mb = S.m - S.base - (Q - 1) - GS;
-    f.nb = S.n - GS - (S.d - S.base);
-    f.fb = S.filled - (S.d - S.base) - GS;
-  } else {
-    f.mb = f.nb = f.fb = kFar;
-  }
-  return f;
-}
-
-__device__ __forceinline__ int32_t fast_test(const Slot& S, const FastOps& f, int32_t& z,
+__device__ __forceinline__ int32_t fast_test(const Slot& S, const pair::FastOps& f, int32_t& z,
                                              int32_t& lo) {
   z = top_gap(S.M);
   lo = low_row(S.M);
@@ -628,7 +557,7 @@ __device__ __forceinline__ int32_t fast_test(const Slot& S, const FastOps& f, in
 // As pair::fix, for whole-lane (four-row) slides.
 template <int H>
 __device__ __forceinline__ bool fix(Slot& S, const Shared* Zp, uint32_t* lds, uint32_t (&U1)[R],
-                                    uint32_t (&Up)[R], int32_t z, int32_t lo, FastOps& f) {
+                                    uint32_t (&Up)[R], int32_t z, int32_t lo, pair::FastOps& f) {
   if (!S.active) return false;
   if (z < GS) {
     const int32_t sl = lo / R;
@@ -642,26 +571,12 @@ __device__ __forceinline__ bool fix(Slot& S, const Shared* Zp, uint32_t* lds, ui
   }
   if (((z + f.mb) | (lo + f.nb)) < 0) return false;
   if (f.fb < 0) {
-    fill_b<H>(S, Zp, lds, S.d + GS - S.base + 64);
+    pair::fill_b<H, Geo>(S, Zp, lds, S.d + GS - S.base + 64);
     f.fb = S.filled - (S.d - S.base) - GS;
   }
   return true;
 }
 
-template <int H>
-__device__ __forceinline__ uint32_t rebase_amount(const Slot& S, int32_t g, uint32_t NT) {
-  const int32_t thr = pair::half_of<H>(NT) - (int32_t)kNegPat + 1;
-  if (!S.active || thr <= kBase + g) return 0u;
-  return (uint32_t)(thr - (kBase + g));
-}
-
-template <int H>
-__device__ __forceinline__ void add_rebase(uint32_t* lds, uint32_t r) {
-  uint32_t* cold = slot_cold<H>(lds);
-  const uint32_t v = pair::cold_get(cold, pair::kCR) + r;
-  if (lane_id() == 0) cold[pair::kCR] = v;
-  wave_lds_fence();
-}
 
 // Runs extensions two at a time until W runs out: W.next(e, ex, rs) (rs:
 // a saved state to resume, or null), W.done(e, result), W.overflow(e,
@@ -719,11 +634,11 @@ __device__ void run(Work& W, uint32_t* lds, const Shared* Zp) {
     int sb = B.active ? prepare<1>(B, Zp, lds, U1, Up) : kGo;
     if ((sa | sb) & (kEnd | kOvf)) {
       if (sa & kEnd)
-        W.done(pair::cold_get(slot_cold<0>(lds), pair::kCe), result<0>(A, Zp, lds, cnt, NT));
+        W.done(pair::cold_get(slot_cold<0>(lds), pair::kCe), pair::result<0, Geo>(A, Zp, lds, cnt, NT));
       if (sa & kOvf)
         W.overflow(pair::cold_get(slot_cold<0>(lds), pair::kCe), save<0>(A, lds, U1, Up, cnt, NT));
       if (sb & kEnd)
-        W.done(pair::cold_get(slot_cold<1>(lds), pair::kCe), result<1>(B, Zp, lds, cnt, NT));
+        W.done(pair::cold_get(slot_cold<1>(lds), pair::kCe), pair::result<1, Geo>(B, Zp, lds, cnt, NT));
       if (sb & kOvf)
         W.overflow(pair::cold_get(slot_cold<1>(lds), pair::kCe), save<1>(B, lds, U1, Up, cnt, NT));
       if (sa & (kEnd | kOvf)) {
@@ -743,7 +658,7 @@ __device__ void run(Work& W, uint32_t* lds, const Shared* Zp) {
     if (!A.active) NT = pair::with_half<0>(NT, kNegPat + 1500u);
     if (!B.active) NT = pair::with_half<1>(NT, kNegPat + 1500u);
     {
-      const uint32_t Rb = rebase_amount<0>(A, g, NT) | (rebase_amount<1>(B, g, NT) << 16);
+      const uint32_t Rb = pair::rebase_amount<0>(A, g, NT) | (pair::rebase_amount<1>(B, g, NT) << 16);
       if (Rb) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -751,8 +666,8 @@ __device__ void run(Work& W, uint32_t* lds, const Shared* Zp) {
           Up[r] = pair::pk_sub_sat(Up[r], Rb);
         }
         NT -= Rb;
-        if (Rb & 0xffffu) add_rebase<0>(lds, Rb & 0xffffu);
-        if (Rb >> 16) add_rebase<1>(lds, Rb >> 16);
+        if (Rb & 0xffffu) pair::add_rebase<0, Geo>(lds, Rb & 0xffffu);
+        if (Rb >> 16) pair::add_rebase<1, Geo>(lds, Rb >> 16);
       }
     }
     A.cnt32 += pair::count_half<0>(cnt);
@@ -769,7 +684,7 @@ __device__ void run(Work& W, uint32_t* lds, const Shared* Zp) {
         group<true, GS>(A, B, U1, Up, upv, cnt, NT, TP, KX, G1, GB1, ONE);
       continue;
     }
-    FastOps fa = fast_ops(A), fb = fast_ops(B);
+    pair::FastOps fa = pair::fast_ops<Q, GS>(A), fb = pair::fast_ops<Q, GS>(B);
     for (int32_t left = stretch; left > 0; --left) {
       int32_t za, la, zb, lb;
       const int32_t ta = fast_test(A, fa, za, la);

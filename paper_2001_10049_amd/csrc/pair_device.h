@@ -268,17 +268,29 @@ struct Shared {
 // LDS of one wave: both slots' rings, then both slots' cold records
 constexpr int WAVE_WORDS = 2 * SLOT_WORDS + 2 * kCWords;
 
-template <int H>
+// LDS geometry of a packed tier (this one, and the wider windows' packed
+// tiers, which share the helpers below): per slot a b ring of RING words with
+// MIR of them mirrored after it and an a ring of RA bytes, then both slots'
+// cold records
+template <int RING_, int MIR_, int RA_>
+struct Geometry {
+  static constexpr int RING = RING_, MASK = RING_ - 1, MIR = MIR_, RA = RA_;
+  static constexpr int SLOT_WORDS = RING_ + MIR_ + RA_ / 4;
+  static constexpr int WAVE_WORDS = 2 * SLOT_WORDS + 2 * kCWords;
+};
+using Geo = Geometry<RING, MIR, RA>;
+
+template <int H, class G = Geo>
 __device__ __forceinline__ uint32_t* slot_ring(uint32_t* lds) {
-  return lds + H * SLOT_WORDS;
+  return lds + H * G::SLOT_WORDS;
 }
-template <int H>
+template <int H, class G = Geo>
 __device__ __forceinline__ uint32_t* slot_cold(uint32_t* lds) {
-  return lds + 2 * SLOT_WORDS + H * kCWords;
+  return lds + 2 * G::SLOT_WORDS + H * kCWords;
 }
-template <int H>
+template <int H, class G = Geo>
 __device__ __forceinline__ const uint32_t* slot_cold(const uint32_t* lds) {
-  return lds + 2 * SLOT_WORDS + H * kCWords;
+  return lds + 2 * G::SLOT_WORDS + H * kCWords;
 }
 __device__ __forceinline__ uint32_t cold_get(const uint32_t* c, int k) {
   return __builtin_amdgcn_readfirstlane(c[k]);
@@ -305,10 +317,11 @@ __device__ __forceinline__ uint32_t code_in(uint32_t w, int32_t o, int32_t dr, i
 // bonus of a row whose a-code is c against b_j: mismatch + 2g, plus 1 -
 // mismatch when c = code(b_j); 0 outside 1..n.  Refilled 64 j at a time from
 // the prefetched word, the next chunk's word loaded meanwhile.
-template <int H>
-__device__ __forceinline__ void fill_b(Slot& S, const Shared* Zp, uint32_t* lds, int32_t jhi) {
-  uint32_t* ring = slot_ring<H>(lds);
-  const uint32_t* cold = slot_cold<H>(lds);
+template <int H, class G = Geo, class SlotT = Slot>
+__device__ __forceinline__ void fill_b(SlotT& S, const Shared* Zp, uint32_t* lds, int32_t jhi) {
+  constexpr int RING = G::RING, MASK = G::MASK, MIR = G::MIR;
+  uint32_t* ring = slot_ring<H, G>(lds);
+  const uint32_t* cold = slot_cold<H, G>(lds);
   const uint32_t* wb = cold_ptr(cold, kCwbLo);
   const int32_t ob = (int32_t)cold_get(cold, kCob), dirb = (int32_t)cold_get(cold, kCdirb);
   const uint32_t comp = cold_get(cold, kCcomp);
@@ -359,16 +372,13 @@ __device__ __forceinline__ uint32_t shr1(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x138, 0xF, 0xF, true);
 }
 
-// Starts extension e in slot H: the origin is live with value X + 1024 and
-// thr = g + 1024 for antidiagonal 1.
-template <int H>
-__device__ __forceinline__ void start(Slot& S, const Shared* Zp, uint32_t* lds, uint32_t e,
-                                   const Ext& ex, uint32_t& U1, uint32_t& Up, uint32_t& cnt,
-                                   uint32_t& NT, uint32_t& KX) {
-  const int lane = lane_id();
-  uint32_t* cold = slot_cold<H>(lds);
-  XD_PAIR_EVENT(8);
-  if (lane == 0) {
+// Slot H's cold record for extension e: its read set-up, the a ring's fill
+// level and the slot's rebase total.
+template <int H, class G = Geo>
+__device__ __forceinline__ void cold_start(uint32_t* lds, uint32_t e, const Ext& ex,
+                                           uint32_t filled_a, uint32_t rebase) {
+  uint32_t* cold = slot_cold<H, G>(lds);
+  if (lane_id() == 0) {
     cold[kCe] = e;
     cold[kCwaLo] = (uint32_t)(uintptr_t)ex.wa;
     cold[kCwaHi] = (uint32_t)((uintptr_t)ex.wa >> 32);
@@ -379,10 +389,21 @@ __device__ __forceinline__ void start(Slot& S, const Shared* Zp, uint32_t* lds, 
     cold[kCdir] = (uint32_t)ex.dir;
     cold[kCdirb] = (uint32_t)ex.dirb;
     cold[kCcomp] = ex.comp;
-    cold[kCfilledA] = 0xffffffffu;  // -1
-    cold[kCR] = 0;
+    cold[kCfilledA] = filled_a;
+    cold[kCR] = rebase;
   }
   wave_lds_fence();
+}
+
+// Starts extension e in slot H: the origin is live with value X + 1024 and
+// thr = g + 1024 for antidiagonal 1.
+template <int H>
+__device__ __forceinline__ void start(Slot& S, const Shared* Zp, uint32_t* lds, uint32_t e,
+                                   const Ext& ex, uint32_t& U1, uint32_t& Up, uint32_t& cnt,
+                                   uint32_t& NT, uint32_t& KX) {
+  const int lane = lane_id();
+  XD_PAIR_EVENT(8);
+  cold_start<H>(lds, e, ex, 0xffffffffu, 0u);  // a ring empty: filled to row -1
   S.active = 1;
   S.d = 0;
   S.base = 0;
@@ -415,13 +436,13 @@ __device__ __forceinline__ void park(uint32_t& U1, uint32_t& Up, uint32_t& cnt, 
 }
 
 // The finished extension's result.
-template <int H>
-__device__ __forceinline__ ExtOut result(const Slot& S, const Shared* Zp, const uint32_t* lds,
+template <int H, class G = Geo, class SlotT = Slot>
+__device__ __forceinline__ ExtOut result(const SlotT& S, const Shared* Zp, const uint32_t* lds,
                                       uint32_t cnt, uint32_t NT) {
   const uint64_t cells = wave_sum_u64v((uint64_t)S.cnt32 + count_half<H>(cnt));
   const int32_t thr = half_of<H>(NT) - (int32_t)kNegPat + 1;  // for antidiagonal d + 1
   ExtOut o;
-  o.best = thr - Zp->g * (S.d + 1) - kBase + (int32_t)cold_get(slot_cold<H>(lds), kCR);
+  o.best = thr - Zp->g * (S.d + 1) - kBase + (int32_t)cold_get(slot_cold<H, G>(lds), kCR);
   o.bi = S.bi;
   o.bj = S.dstar - S.bi;
   o.flags = kExtDone;
@@ -622,8 +643,8 @@ __device__ __forceinline__ void group(Slot& A, Slot& B, uint32_t& U1, uint32_t& 
 
 // The amount that brings slot H's threshold back to 1024 + g (0 when it is
 // there or the slot is idle); run subtracts it from the slot's values too.
-template <int H>
-__device__ __forceinline__ uint32_t rebase_amount(const Slot& S, int32_t g, uint32_t NT) {
+template <int H, class SlotT = Slot>
+__device__ __forceinline__ uint32_t rebase_amount(const SlotT& S, int32_t g, uint32_t NT) {
   const int32_t thr = half_of<H>(NT) - (int32_t)kNegPat + 1;
   if (!S.active || thr <= kBase + g) return 0u;
   return (uint32_t)(thr - (kBase + g));
@@ -635,9 +656,9 @@ __device__ __forceinline__ uint32_t pk_sub_sat(uint32_t v, uint32_t r) {
   return o;
 }
 
-template <int H>
+template <int H, class G = Geo>
 __device__ __forceinline__ void add_rebase(uint32_t* lds, uint32_t r) {
-  uint32_t* cold = slot_cold<H>(lds);
+  uint32_t* cold = slot_cold<H, G>(lds);
   const uint32_t v = cold_get(cold, kCR) + r;
   if (lane_id() == 0) cold[kCR] = v;
   wave_lds_fence();
@@ -654,12 +675,14 @@ struct FastOps {
 };
 constexpr int32_t kFar = 1 << 29;
 
-__device__ __forceinline__ FastOps fast_ops(const Slot& S) {
+// (Q window rows, G antidiagonals a group)
+template <int Q = 64, int G = GS, class SlotT = Slot>
+__device__ __forceinline__ FastOps fast_ops(const SlotT& S) {
   FastOps f;
   if (S.active) {
-    f.mb = S.m - S.base - 63 - GS;
-    f.nb = S.n - GS - (S.d - S.base);
-    f.fb = S.filled - (S.d - S.base) - GS;
+    f.mb = S.m - S.base - (Q - 1) - G;
+    f.nb = S.n - G - (S.d - S.base);
+    f.fb = S.filled - (S.d - S.base) - G;
   } else {
     f.mb = f.nb = f.fb = kFar;
   }
