@@ -264,6 +264,30 @@ def test_packed_128_window_parity(wl):
     assert_same(got, oracle.align_workload(w), label="packed 128 " + wl)
 
 
+@pytest.mark.parametrize("wl", ["edge", "band", "flank"])
+def test_packed_256_window_parity(wl):
+    # every extension with X > 1 starts in the 256-cell window: the packed
+    # four-rows-per-lane kernel from a seed (not from a saved state) for
+    # X <= 4096, the 32-bit kernel past that; bands that outgrow 256 rows
+    # leave their state for the 512-cell window
+    w = {"edge": edge_workload, "band": band_workload, "flank": random_flank_workload}[wl]()
+    print("packed 256", wl, flush=True)
+    xd.profile_enable(True)
+    xd.profile_read(reset=True)
+    store = xd.ReadStore.from_workload(w)
+    pairs, seeds, x = xd.workload_tensors(w, "cuda")
+    out = xd.align_batch(store, pairs, seeds, x=x, k=w.k, persistent=True,
+                         tuning=dict(x_tier1=1, x_tier2=1))
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    prof = xd.profile_read(reset=True)
+    xd.profile_enable(False)
+    store.close()
+    assert_same(got, oracle.align_workload(w), label="packed 256 " + wl)
+    # nothing started below the 256-cell window
+    assert prof["to_tier2"] == 0 and prof["to_tier3"] == 0, prof
+
+
 def test_persistent_edge_and_scoring():
     w = edge_workload()
     store = xd.ReadStore.from_workload(w)
