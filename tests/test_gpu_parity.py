@@ -376,3 +376,29 @@ def test_wide_windows_parity(form):
         # the seed (both paths are taken here)
         moves = sum(prof[f] for f in ("to_tier2", "to_tier3", "to_tier4", "to_tier5"))
         assert 0 < prof["resumed"] < moves, prof
+
+
+@pytest.mark.parametrize("form", ["plain", "persistent"])
+def test_wide_windows_general_scores(form):
+    # the same flanks under +2/-3/-2 with X doubled (bands of the same widths:
+    # 100-500 cells): the 32-bit kernels of every window, their saved states
+    # and resumes, against the oracle
+    w = random_flank_workload()
+    w.x = (w.x * 2).astype(np.int32)
+    print("wide windows +2/-3/-2", form, flush=True)
+    ref = oracle.align_workload(w, match=2, mismatch=-3, gap=-2)
+    xd.profile_enable(True)
+    xd.profile_read(reset=True)
+    store = xd.ReadStore.from_workload(w)
+    pairs, seeds, xs = xd.workload_tensors(w, "cuda")
+    out = xd.align_batch(store, pairs, seeds, x=xs, k=w.k, match=2, mismatch=-3, gap=-2,
+                         persistent=form == "persistent")
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    prof = xd.profile_read(reset=True)
+    xd.profile_enable(False)
+    store.close()
+    assert_same(got, ref, label="wide +2/-3/-2 " + form)
+    assert prof["to_tier3"] > 0 and prof["to_tier4"] > 0, prof
+    moves = sum(prof[f] for f in ("to_tier2", "to_tier3", "to_tier4", "to_tier5"))
+    assert 0 < prof["resumed"] < moves, prof
