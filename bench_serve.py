@@ -30,7 +30,7 @@ def main():
     ap.add_argument("--max-size", type=int, default=10000)
     ap.add_argument("--workload", default="c5")
     ap.add_argument("--budget-mib", type=int, default=2048)
-    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--max-batch", type=int, default=65536)
     ap.add_argument("--seed", type=int, default=7)
     args = ap.parse_args()
@@ -42,7 +42,7 @@ def main():
 
 
 def run(rate=2000.0, seconds=20.0, warmup=2.0, max_size=10000, workload="c5", budget_mib=2048,
-        slots=4, max_batch=65536, seed=7) -> dict:
+        slots=3, max_batch=65536, seed=7) -> dict:
     """One serving run; returns the JSON record."""
     args = argparse.Namespace(rate=rate, seconds=seconds, warmup=warmup, max_size=max_size,
                               workload=workload, budget_mib=budget_mib, slots=slots,

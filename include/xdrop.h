@@ -403,7 +403,8 @@ typedef struct xd_server xd_server;
 
 typedef struct {
   uint64_t hbm_budget_bytes; /* device bytes for requests in flight (0 = 1 GiB) */
-  int32_t slots;             /* batches in flight at once, 1..64 (0 = 4) */
+  int32_t slots;             /* batches in flight at once, 1..64 (0 = 3: one hardware
+                                queue each beside the default stream's) */
   int32_t max_batch_tasks;   /* tasks per batch (0 = 262144) */
   int32_t max_pending;       /* queued requests before submit says XD_EAGAIN (0 = 65536) */
   int32_t k, match, mismatch, gap; /* as for xd_align_batch */

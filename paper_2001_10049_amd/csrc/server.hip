@@ -28,6 +28,15 @@
 
 namespace {
 
+// Default batch slots.  HIP spreads a process's streams over a few hardware
+// queues (four by default), one of which also serves the default stream:
+// with three slot streams no two batches need share a queue, where a batch
+// would wait behind the other's kernels.  Measured on Poisson arrivals of
+// 2,000 requests/s (1-10,000 pairs each, reads of 1-100 kbp): three slots
+// gave p50 4.6 ms and p99 8.9 ms, four 5.2 and 11.1, eight 7.2 and 15.2,
+// at the same throughput.
+constexpr int32_t kDefaultSlots = 3;
+
 double now_s() {
   using namespace std::chrono;
   return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -284,7 +293,7 @@ uint64_t xd_server_fixed_bytes(const xd_store* store, const xd_server_config* cf
   if (!store || !cfg) return 0;
   uint32_t max_len = 0;
   if (xd_store_info(store, nullptr, nullptr, &max_len) != XD_OK) return 0;
-  const int32_t slots = cfg->slots <= 0 ? 4 : cfg->slots;
+  const int32_t slots = cfg->slots <= 0 ? kDefaultSlots : cfg->slots;
   const uint32_t blocks = cfg->tuning.band_blocks > 0 ? (uint32_t)cfg->tuning.band_blocks : 1u;
   return (uint64_t)slots * xd_internal_band_bytes(max_len, blocks);
 }
@@ -304,7 +313,7 @@ int xd_server_create(const xd_store* store, const xd_server_config* cfg, xd_serv
   S->store = store;
   S->cfg = *cfg;
   if (!S->cfg.hbm_budget_bytes) S->cfg.hbm_budget_bytes = 1ull << 30;
-  if (S->cfg.slots <= 0) S->cfg.slots = 4;
+  if (S->cfg.slots <= 0) S->cfg.slots = kDefaultSlots;
   if (S->cfg.max_batch_tasks <= 0) S->cfg.max_batch_tasks = 1 << 18;
   if (S->cfg.max_pending <= 0) S->cfg.max_pending = 1 << 16;
   if (S->cfg.tuning.band_blocks <= 0) S->cfg.tuning.band_blocks = 1;
