@@ -107,6 +107,10 @@ def run(rate=2000.0, seconds=20.0, warmup=2.0, max_size=10000, workload="c5", bu
     win = arrivals >= args.warmup
     lat = np.array([results[q][0]["t_done"] - results[q][0]["t_submit"]
                     for q in range(n_req)])[win]
+    # the two parts of a latency: waiting for admission, then the batch
+    wait = np.array([results[q][0]["t_start"] - results[q][0]["t_submit"]
+                     for q in range(n_req)])[win]
+    run_t = lat - wait
     t_first = min(results[q][0]["t_submit"] for q in range(n_req) if win[q])
     t_last = max(results[q][0]["t_done"] for q in range(n_req) if win[q])
     span = t_last - t_first
@@ -118,6 +122,10 @@ def run(rate=2000.0, seconds=20.0, warmup=2.0, max_size=10000, workload="c5", bu
         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
         "mean_ms": round(float(lat.mean()) * 1e3, 3),
+        "wait_p50_ms": round(float(np.percentile(wait, 50)) * 1e3, 3),
+        "wait_p99_ms": round(float(np.percentile(wait, 99)) * 1e3, 3),
+        "batch_p50_ms": round(float(np.percentile(run_t, 50)) * 1e3, 3),
+        "batch_p99_ms": round(float(np.percentile(run_t, 99)) * 1e3, 3),
         "pairs_per_s": round(pairs / span, 1), "gcups": round(cells / span / 1e9, 2),
         "offered_pairs_per_s": round(float(sizes[win].sum()) / args.seconds, 1),
         "requests": int(win.sum()), "rate": args.rate, "failed_tasks": bad,
