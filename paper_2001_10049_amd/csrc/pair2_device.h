@@ -269,8 +269,6 @@ __device__ __forceinline__ void park(uint32_t& U1e, uint32_t& U1o, uint32_t& Upe
   KX = pair::with_half<H>(KX, 0x7fffu);
 }
 
-// The finished extension's result.
-
 // Slot H's state where its band outgrew the window, in the 32-bit tiers'
 // units (as pair::save; 128 rows: row 2l from the even register of lane l,
 // row 2l + 1 from the odd one; the top row of the antidiagonal before the

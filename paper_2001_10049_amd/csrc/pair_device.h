@@ -254,7 +254,6 @@ __device__ __forceinline__ uint32_t with_half(uint32_t v, uint32_t h) {
   return H ? ((v & 0x0000ffffu) | (h << 16)) : ((v & 0xffff0000u) | (h & 0xffffu));
 }
 
-
 // ---- the two-slot runner ----------------------------------------------------
 
 // Scalars shared by both slots (read from memory where needed).
